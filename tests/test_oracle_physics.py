@@ -1,0 +1,262 @@
+"""Physics pins of the FP64 oracle against what the paper and the mathematics
+fix: free-space Green's function, plane-wave attenuation / dispersion
+(Sec. 4.1, Fig. 2), two-stage C-PML reflection (Secs. 4.2-4.3, Fig. 3) and
+nonlinear steepening against the exact pre-shock simple wave (Sec. 4.5)."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import physics, relaxation, solver
+
+C0 = 1540.0
+
+
+# --------------------------------------------------------- Green's function ---
+
+def _green_run(ppw, cfl, f0=2e6, dists=(5, 8)):
+    lam = ppw
+    n = int(2 * (max(dists) * lam + 20) + 2 * 4 * lam)
+    prob = W.homogeneous((n, n), L=1, row=W.lossless_row(1), nb=(4 * lam,) * 2, ntr=(3 * lam,) * 2,
+                         f0=f0, ppw=ppw, cfl=cfl)
+    prob.beta = np.full(prob.c.shape, 0.5, np.float32)
+    h, dt = prob.h, prob.dt
+    nt = int((max(dists) * lam * h / C0 + 12 * 3 / (4 * f0)) / dt) + 50
+    sig = W.gaussian_pulse(nt, dt, f0, 3, amp=1.0)
+    ctr = n // 2
+    prob.signals = sig[None]
+    prob.src_idx = prob.flat(np.array([ctr]), np.array([ctr]))
+    prob.src_sig = np.zeros(1, np.int32)
+    prob.src_w = np.ones(1, np.float32)
+    rs = [(d * lam, 0) for d in dists] + [(int(round(d * lam / np.sqrt(2))),) * 2 for d in dists]
+    prob.rcv_idx = prob.flat(np.array([ctr + a for a, b in rs]), np.array([ctr + b for a, b in rs]))
+    _, tr = solver.run(prob, nt)
+    # Additive injection of s_n after the pressure update is a source term
+    # dp/dt += (h^2/dt) s(t) delta(x) with s_n at t = (n+1/2) dt; p of trace row n
+    # is at (n+1) dt.  p = G * d/dt(source).
+    N = 8 * nt
+    s = np.zeros(N)
+    s[:nt] = sig
+    S = np.fft.rfft(s)
+    w = 2 * np.pi * np.fft.rfftfreq(N, dt)
+    errs = []
+    for k, (a, b) in enumerate(rs):
+        r = np.hypot(a, b) * h
+        P = np.zeros_like(S)
+        P[1:] = physics.greens_2d_freq(w[1:], r, C0) * 1j * w[1:] * (h * h / dt) * S[1:] * np.exp(1j * w[1:] * dt / 2)
+        pa = np.fft.irfft(P, N)[:nt]
+        errs.append(np.linalg.norm(tr[:, k] - pa) / np.linalg.norm(pa))
+    return np.array(errs)
+
+
+def test_lossless_point_source_matches_2d_greens_function(oracle_lib):
+    """Lossless homogeneous medium, 12 ppw, CFL 0.4: traces at 5 and 8
+    wavelengths (on axis and diagonal) match the analytic 2D Green's function
+    convolution within 1 % (rel L2); halving the time step cuts the error
+    about four-fold (the source term is second order in time)."""
+    e = _green_run(12, 0.4)
+    assert np.all(e < 1e-2), e
+    e2 = _green_run(12, 0.2)
+    assert np.all(e2 < e / 3.0), (e, e2)
+
+
+# ------------------------------------------- attenuation and dispersion (E1) ---
+
+def _plane_wave_measure(row, L, f0, scheme=1, ppw=12, cfl=0.4, width=64, dist_lam=10):
+    """Plane pulse from a full-width line source; attenuation (dB/cm) and
+    phase velocity between two receivers dist_lam wavelengths apart, at the
+    spectral line nearest f0 (Sec. 4.1 measurement)."""
+    lam = ppw
+    nb, ntr = 4 * lam, 3 * lam
+    nx = width + 2 * nb
+    ys = nb + 4
+    y1 = ys + 2 * lam
+    y2 = y1 + dist_lam * lam
+    ny = y2 + 2 * lam + nb
+    prob = W.homogeneous((nx, ny), L=L, row=row, nb=(nb, nb), ntr=(ntr, ntr), f0=f0, ppw=ppw, cfl=cfl)
+    prob.beta = np.full(prob.c.shape, 0.5, np.float32)
+    prob.relax_scheme = scheme
+    h, dt = prob.h, prob.dt
+    npulse = W.pulse_length(dt, f0, 3)
+    nt = int((y2 - ys) * h / C0 / dt) + npulse + 200
+    xs = np.arange(nx)
+    prob.src_idx = prob.flat(xs, np.full_like(xs, ys))
+    prob.src_sig = np.zeros(nx, np.int32)
+    prob.src_w = np.ones(nx, np.float32)
+    prob.signals = W.gaussian_pulse(npulse, dt, f0, 3, 1.0)[None]
+    cx = nx // 2
+    prob.rcv_idx = prob.flat(np.array([cx, cx]), np.array([y1, y2]))
+    _, tr = solver.run(prob, nt)
+    N = 4 * nt
+    P1, P2 = np.fft.rfft(tr[:, 0], N), np.fft.rfft(tr[:, 1], N)
+    f = np.fft.rfftfreq(N, dt)
+    k = np.argmin(np.abs(f - f0))
+    dx = (y2 - y1) * h
+    att = np.log(np.abs(P1[k]) / np.abs(P2[k])) / dx * relaxation.NP_PER_M_TO_DB_PER_CM
+    w = 2 * np.pi * f[k]
+    tau0 = dx / C0
+    tau = tau0 - np.angle(P2[k] / P1[k] * np.exp(1j * w * tau0)) / w
+    return f[k], att, dx / tau
+
+
+FREQS = [1e6, 2e6, 5e6, 10e6, 20e6]
+
+
+def test_attenuation_and_dispersion_follow_power_law(oracle_lib):
+    """Sec. 4.1 / Fig. 2: a pulse propagated 10 wavelengths at 12 ppw,
+    CFL 0.4, in the fitted alpha0 = 0.5 dB/cm/MHz, y = 1 medium (two
+    mechanisms): measured attenuation within 1 % and phase velocity within
+    5e-5 of the dispersion relation (Eq. dispersion_relations), hence within
+    the paper's 5 % / 0.5 % of alpha0 f^y and its Kramers-Kronig velocity."""
+    row = W.tissue_row(0.5, 1.0, 2, 2e6)
+    for f0 in FREQS:
+        fk, att, vel = _plane_wave_measure(row, 2, f0)
+        a_an, c_an = relaxation.model_attenuation_velocity(np.array([fk]), C0, np.array(row), 2)
+        assert abs(att / a_an[0] - 1) < 0.01, (f0, att, a_an)
+        assert abs(vel / c_an[0] - 1) < 5e-5, (f0, vel, c_an)
+        assert abs(att / physics.power_law_db_cm(fk, 0.5, 1.0) - 1) < 0.05
+        assert abs(vel / physics.kk_phase_velocity(fk, 0.5, 1.0, C0, 2e6) - 1) < 0.005
+
+
+def test_attenuation_y_not_one_and_four_mechanisms(oracle_lib):
+    """Same measurement for a y = 1.3 law with four mechanisms (the kind of
+    tuple the heterogeneous 2D workload uses) at 3 and 12 MHz."""
+    row = W.tissue_row(1.5, 1.3, 4, 3e6)
+    for f0 in (3e6, 12e6):
+        fk, att, vel = _plane_wave_measure(row, 4, f0)
+        a_an, c_an = relaxation.model_attenuation_velocity(np.array([fk]), C0, np.array(row), 4)
+        assert abs(att / a_an[0] - 1) < 0.01
+        assert abs(vel / c_an[0] - 1) < 2e-4
+        assert abs(att / physics.power_law_db_cm(fk, 1.5, 1.3) - 1) < 0.05
+
+
+def test_printed_recursion_loses_attenuation(oracle_lib):
+    """The literal update-then-use recursion (Eq. relaxation_psi entering
+    the step that produced it) applies psi half a step late: at 12 ppw /
+    CFL 0.4 the measured attenuation falls 10-30 % below the dispersion
+    relation (this is why the time-centred evaluation is the default)."""
+    row = W.tissue_row(0.5, 1.0, 2, 2e6)
+    fk, att, vel = _plane_wave_measure(row, 2, 2e6, scheme=0)
+    a_an, _ = relaxation.model_attenuation_velocity(np.array([fk]), C0, np.array(row), 2)
+    assert -0.30 < att / a_an[0] - 1 < -0.10
+
+
+# ----------------------------------------------------- C-PML reflection (E2/E3) ---
+
+def _reflection_db(row, L, angles, ppw=16, cfl=0.2, ntr_l=3, nbd_l=1, D_l=1.0, f0=2e6, ext_l=20,
+                   margin_l=2):
+    """Reflection of the bottom two-stage layer at the given incidence
+    angles: run A has the layer D_l wavelengths below a point source; run B
+    is identical but ext_l wavelengths deeper (no reflection in the window).
+    R = max|p_A - p_B| at a receiver at the source depth, offset 2 D tan(theta),
+    over the direct-wave peak at the image distance 2 D / cos(theta)."""
+    lam = ppw
+    nb, ntr = (ntr_l + nbd_l) * lam, ntr_l * lam
+    D = int(round(D_l * lam))
+    offs = [int(round(2 * D * np.tan(np.radians(a)))) for a in angles]
+    rimg = [2 * D / np.cos(np.radians(a)) for a in angles]
+    half = max(max(offs), int(max(rimg))) + margin_l * lam
+    nx = 2 * half + 2 * nb + 1
+    top = margin_l * lam
+    ny_a = nb + top + D + nb
+    res = {}
+    for name, ny in (("A", ny_a), ("B", ny_a + ext_l * lam)):
+        prob = W.homogeneous((nx, ny), L=L, row=row, nb=(nb, nb), ntr=(ntr, ntr), f0=f0, ppw=ppw, cfl=cfl)
+        h, dt = prob.h, prob.dt
+        sx, sy = nx // 2, nb + top
+        npulse = W.pulse_length(dt, f0, 3)
+        nt = int((max(rimg) + 4 * lam) * h / C0 / dt) + npulse
+        prob.src_idx = prob.flat(np.array([sx]), np.array([sy]))
+        prob.src_sig = np.zeros(1, np.int32)
+        prob.src_w = np.ones(1, np.float32)
+        prob.signals = W.gaussian_pulse(npulse, dt, f0, 3, 1.0)[None]
+        rx = np.array([sx + o for o in offs] + [sx - int(round(r)) for r in rimg])
+        prob.rcv_idx = prob.flat(rx, np.full(rx.size, sy))
+        _, res[name] = solver.run(prob, nt)
+    A, B = res["A"], res["B"]
+    n = len(angles)
+    return np.array([20 * np.log10(np.abs(A[:, k] - B[:, k]).max() / np.abs(B[:, n + k]).max())
+                     for k in range(n)])
+
+
+def test_cpml_reflection_special_case_and_fitted_tissue(oracle_lib):
+    """Secs. 4.2-4.3 at 16 ppw, CFL 0.2, 3 lambda transition + 1 lambda
+    bound: the C-PML special case (lossless interior) reflects below -60 dB at
+    normal incidence and below -49 dB up to 60 degrees; with the fitted
+    two-mechanism tissue the two-stage layer stays below -49 dB at normal
+    incidence, and a 5 + 1 lambda layer is better than 3 + 1."""
+    r = _reflection_db(W.lossless_row(1), 1, (0, 30, 45, 60))
+    assert r[0] < -60, r
+    assert np.all(r < -49), r
+    row = W.tissue_row(0.5, 1.0, 2, 2e6)
+    r31 = _reflection_db(row, 2, (0,))[0]
+    assert r31 < -49, r31
+    r51 = _reflection_db(row, 2, (0,), ntr_l=5)[0]
+    assert r51 < r31, (r31, r51)
+
+
+def test_cpml_reflection_table2_tissue_recorded(oracle_lib):
+    """With Table 2 verbatim (kappa1 = 0.835, kappa2 = 1.19 and very fast
+    nabla_1 mechanisms) the layer's stretch ratio moves from the tissue's
+    towards 1, so the impedance changes inside the layer: measured about
+    -38 dB at normal incidence (recorded finding; the paper's -49 dB is
+    reached by the special case and the fitted tissue above)."""
+    r = _reflection_db(W.TABLE2_ROW, 2, (0,))[0]
+    assert -45 < r < -30, r
+
+
+# ------------------------------------------------ nonlinear steepening (E5) ---
+
+def test_nonlinear_plane_wave_matches_exact_simple_wave(oracle_lib):
+    """Sec. 4.5: lossless plane pulse (1 MHz, 4 cycles), 20 ppw, CFL 0.4.
+    The waveform recorded at receiver 1 is propagated to receiver 2 with the
+    exact pre-shock simple-wave solution of the same equations (each value
+    travels at 1/sqrt(rho(p) kappa(p)), Eqs. state1 / state2, so the
+    effective coefficient is beta - 1); at sigma ~ 0.35 the first four
+    harmonic levels agree within 1 dB.  With the nonlinear terms switched off
+    (beta = 1/2 in Eq. general6 and amplitude far smaller) the second
+    harmonic is absent, so the match is not a linear-propagation artefact."""
+    p0, f0, ppw, cfl, beta = 2e6, 1e6, 20, 0.4, 3.5
+    lam = ppw
+    nb, ntr = 4 * lam, 3 * lam
+    nx = 48 + 2 * nb
+    ys = nb + 4
+    y1 = ys + 3 * lam
+    dist_lam = 26
+    y2 = y1 + dist_lam * lam
+    ny = y2 + 2 * lam + nb
+    prob = W.homogeneous((nx, ny), L=1, row=W.lossless_row(1), nb=(nb, nb), ntr=(ntr, ntr), f0=f0,
+                         ppw=ppw, cfl=cfl, beta=beta)
+    h, dt = prob.h, prob.dt
+    npulse = W.pulse_length(dt, f0, 4)
+    nt = int((y2 - ys) * h / C0 / dt) + npulse + 100
+    xs = np.arange(nx)
+    prob.src_idx = prob.flat(xs, np.full_like(xs, ys))
+    prob.src_sig = np.zeros(nx, np.int32)
+    prob.src_w = np.ones(nx, np.float32)
+    sig = W.gaussian_pulse(npulse, dt, f0, 4, 1.0)
+    cx = nx // 2
+    prob.rcv_idx = prob.flat(np.array([cx, cx]), np.array([y1, y2]))
+    # amplitude calibration with a quasi-linear run: peak p0 at receiver 1
+    prob.signals = sig[None]
+    _, tr = solver.run(prob, y1 * 0 + int((y1 - ys) * h / C0 / dt) + npulse)
+    prob.signals = (sig * p0 / np.abs(tr[:, 0]).max())[None].astype(np.float32)
+    _, tr = solver.run(prob, nt)
+    t = (np.arange(nt) + 1) * dt
+    kap0 = 1.0 / (1000.0 * C0 ** 2)
+    dist = (y2 - y1) * h
+    pex = physics.simple_wave_propagate(t, tr[:, 0], dist, 1000.0, kap0, beta)
+    sigma = (beta - 1) * p0 * kap0 * (2 * np.pi * f0 / C0) * dist
+    assert 0.3 < sigma < 0.45
+    N = 8 * nt
+    f = np.fft.rfftfreq(N, dt)
+    F2, FE = np.abs(np.fft.rfft(tr[:, 1], N)), np.abs(np.fft.rfft(pex, N))
+    for n in range(1, 5):
+        k = np.argmin(np.abs(f - n * f0))
+        assert abs(20 * np.log10(F2[k] / FE[k])) < 1.0, n
+    # the generated second harmonic is a real nonlinear effect
+    prob.beta = np.full(prob.c.shape, 0.5, np.float32)
+    prob.signals = (sig * 1e-3)[None].astype(np.float32)
+    _, trl = solver.run(prob, nt)
+    FL = np.abs(np.fft.rfft(trl[:, 1], N))
+    k1, k2 = np.argmin(np.abs(f - f0)), np.argmin(np.abs(f - 2 * f0))
+    assert F2[k2] / F2[k1] > 30 * FL[k2] / FL[k1]

@@ -1,0 +1,284 @@
+"""Seeded synthetic inputs shared by the oracle and the GPU path.
+
+This module holds input data and random draws only: grids, medium maps
+(c, rho, beta), tissue labels with their relaxation tuples, source signals and
+positions, receiver positions.  It contains none of the method's arithmetic;
+derived coefficients (stencil weights, memory-variable coefficients, boundary
+profiles) are computed separately by the oracle and by the HIP library.
+
+Relaxation tuples are the paper's Table 2 (alpha0 = 0.5 dB/cm/MHz, y = 1,
+two mechanisms) or entries of tissue_fits.json, written by
+oracle/make_tissue_fits.py with the paper's fitting objective (Sec. 4.1).
+
+The paper's 2D and 3D application datasets (a segmented Visible Human abdomen
+and a micro-CT rat skull) are not available; configs 2 and 3 are synthetic
+stand-ins with the shapes, property ranges and structure stated for them.
+"""
+import json
+import os
+from dataclasses import dataclass, field
+from typing import Optional, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+
+# Table 2 of the paper: two mechanisms fitted to alpha0 = 0.5 dB/cm/MHz, y = 1.
+# Column order: k1, k2, d1[nu=1,2], d2[nu=1,2], alpha1[nu=1,2], alpha2[nu=1,2].
+TABLE2_ROW = [0.835, 1.19, 9.82e5, 3.26e6, 4.40e4, 1.68e5, 2.83e8, 3.54e9, 8.35e6, 5.10e7]
+
+# Medium without attenuation or dispersion: unit stretch, no mechanisms.
+def lossless_row(L):
+    return [1.0, 1.0] + [0.0] * (4 * L)
+
+
+_FITS = None
+
+
+def tissue_fits():
+    global _FITS
+    if _FITS is None:
+        with open(os.path.join(_HERE, "tissue_fits.json")) as fh:
+            _FITS = json.load(fh)["fits"]
+    return _FITS
+
+
+def tissue_row(alpha0, y, L, f_ref):
+    """Relaxation tuple for alpha0 f^y with L mechanisms (stored fit)."""
+    k = "a%.2f_y%.2f_L%d_f%.1f" % (alpha0, y, L, f_ref / 1e6)
+    return list(tissue_fits()[k]["row"])
+
+
+ALPHA0_GRID = [0.4, 0.6, 0.8, 1.0, 1.2, 1.5]
+Y_GRID = [1.0, 1.1, 1.2, 1.3]
+
+
+@dataclass
+class Problem:
+    """Inputs of one simulation (what create_domain / add_source / add_receivers take).
+
+    Arrays are numpy with shape shape[::-1] (x fastest); flat indices are
+    x + nx * (y + ny * z).
+    """
+    shape: Tuple[int, ...]
+    h: float
+    dt: float
+    n_relax: int
+    c: np.ndarray
+    rho: np.ndarray
+    beta: np.ndarray
+    relax_table: np.ndarray                  # [n_labels, 2 + 4L] float64
+    label: Optional[np.ndarray] = None       # uint8, or None = all label 0
+    bound_cells: Tuple[int, ...] = (0, 0, 0)
+    trans_cells: Tuple[int, ...] = (0, 0, 0)
+    pml_Rc: float = 1e-3
+    pml_npoly: int = 2
+    pml_cp: float = 0.0                      # 0: largest c of the map
+    fd_r: float = 0.0                        # 0: largest c * dt / h
+    relax_scheme: int = 1                    # 0: printed recursion, 1: time-centred
+    src_idx: np.ndarray = field(default_factory=lambda: np.zeros(0, np.int64))
+    src_sig: np.ndarray = field(default_factory=lambda: np.zeros(0, np.int32))
+    src_w: np.ndarray = field(default_factory=lambda: np.zeros(0, np.float32))
+    signals: np.ndarray = field(default_factory=lambda: np.zeros((1, 1), np.float32))
+    rcv_idx: np.ndarray = field(default_factory=lambda: np.zeros(0, np.int64))
+    n_steps: int = 0
+    name: str = ""
+
+    @property
+    def ndim(self):
+        return len(self.shape)
+
+    @property
+    def npts(self):
+        return int(np.prod(self.shape))
+
+    def flat(self, *coords):
+        """Flat index of (x, y[, z]) (arrays allowed)."""
+        idx = np.zeros_like(np.asarray(coords[0]), dtype=np.int64)
+        stride = 1
+        for a, x in enumerate(coords):
+            idx = idx + np.asarray(x, dtype=np.int64) * stride
+            stride *= self.shape[a]
+        return idx
+
+
+def gaussian_pulse(n_t, dt, f0, n_cycles, amp=1.0):
+    """Gaussian-modulated sinusoid (the pulse shape the paper's experiments
+    use).  Sample n belongs to step n, i.e. to t_n = (n + 1/2) dt; envelope
+    standard deviation n_cycles / (4 f0), centred at six deviations."""
+    sig = n_cycles / (4.0 * f0)
+    t0 = 6.0 * sig
+    t = (np.arange(n_t) + 0.5) * dt
+    return (amp * np.sin(2 * np.pi * f0 * (t - t0)) * np.exp(-0.5 * ((t - t0) / sig) ** 2)).astype(np.float32)
+
+
+def pulse_length(dt, f0, n_cycles):
+    """Samples covering the pulse (twelve envelope deviations)."""
+    return int(np.ceil(12.0 * n_cycles / (4.0 * f0) / dt)) + 1
+
+
+def grid_spacing(c_ref, f0, ppw):
+    return c_ref / (ppw * f0)
+
+
+# ---------------------------------------------------------------------------
+# Generic homogeneous problem (tests)
+# ---------------------------------------------------------------------------
+
+def homogeneous(shape, L=2, c=1540.0, rho=1000.0, beta=3.5, row=None, ppw=12, f0=2e6,
+                cfl=0.4, nb=None, ntr=None, n_steps=100, name="homogeneous"):
+    ndim = len(shape)
+    h = grid_spacing(1540.0, f0, ppw)
+    dt = cfl * h / c
+    grid = tuple(shape[::-1])
+    if row is None:
+        row = TABLE2_ROW if L == 2 else lossless_row(L)
+    if nb is None:
+        nb = (0,) * ndim
+    if ntr is None:
+        ntr = tuple(int(round(0.75 * b)) for b in nb)
+    return Problem(shape=tuple(shape), h=h, dt=dt, n_relax=L,
+                   c=np.full(grid, c, np.float32), rho=np.full(grid, rho, np.float32),
+                   beta=np.full(grid, beta, np.float32),
+                   relax_table=np.asarray([row], np.float64), label=None,
+                   bound_cells=tuple(nb), trans_cells=tuple(ntr), n_steps=n_steps, name=name)
+
+
+def random_medium(shape, L, n_labels, seed, nb=8, ntr=6, ppw=12, f0=3e6, cfl=0.4, n_steps=50,
+                  name="random"):
+    """Piecewise-random medium: labels, c, rho, beta drawn per cell (tests)."""
+    rng = np.random.default_rng(seed)
+    ndim = len(shape)
+    grid = tuple(shape[::-1])
+    h = grid_spacing(1540.0, f0, ppw)
+    c = rng.uniform(1450.0, 1620.0, grid).astype(np.float32)
+    rho = rng.uniform(950.0, 1120.0, grid).astype(np.float32)
+    beta = rng.uniform(3.5, 5.5, grid).astype(np.float32)
+    dt = cfl * h / float(c.max())
+    rows = []
+    for k in range(n_labels):
+        a0 = ALPHA0_GRID[rng.integers(len(ALPHA0_GRID))]
+        y = Y_GRID[rng.integers(len(Y_GRID))]
+        rows.append(tissue_row(a0, y, L, 3e6) if L in (2, 3, 4) else lossless_row(L))
+    label = rng.integers(0, n_labels, grid).astype(np.uint8)
+    return Problem(shape=tuple(shape), h=h, dt=dt, n_relax=L, c=c, rho=rho, beta=beta,
+                   relax_table=np.asarray(rows, np.float64), label=label,
+                   bound_cells=(nb,) * ndim, trans_cells=(ntr,) * ndim, n_steps=n_steps, name=name)
+
+
+def random_state(ndim, L, shape, seed, scale=1.0):
+    """Seeded random initial state (p, v, psi1, psi2) in float32, scaled to
+    acoustic magnitudes: p ~ scale * 1e5 Pa, v ~ p / (rho c), psi ~ v / h."""
+    rng = np.random.default_rng(seed)
+    grid = tuple(shape[::-1])
+    p = (scale * 1e5 * rng.standard_normal(grid)).astype(np.float32)
+    v = (scale * 1e5 / 1.5e6 * rng.standard_normal((ndim,) + grid)).astype(np.float32)
+    psi1 = (scale * 1e5 * 1e-2 * rng.standard_normal((ndim, L) + grid)).astype(np.float32)
+    psi2 = (scale * 1e5 / 1.5e6 * 1e2 * rng.standard_normal((ndim, L) + grid)).astype(np.float32)
+    return p, v, psi1, psi2
+
+
+# ---------------------------------------------------------------------------
+# Workload 1: plain 2D, 384^2 interior + 4 wavelength boundary, water, L = 2
+# ---------------------------------------------------------------------------
+
+def plain_2d(interior=384, ppw=12, f0=2e6, cfl=0.4, n_steps=1000, n_rcv=64, seed=1):
+    """384x384 interior + 48-cell (3 lambda transition + 1 lambda bound)
+    boundary each side; water c 1540, rho 1000, beta 3.5; L = 2 fitted to
+    0.5 dB/MHz^1.1/cm; 12 ppw at 2 MHz, CFL 0.4; 3-cycle line source; 1000
+    steps; 64 receivers.  seed is unused (the workload is deterministic)."""
+    lam = ppw
+    nb, ntr = 4 * lam, 3 * lam
+    n = interior + 2 * nb
+    h = grid_spacing(1540.0, f0, ppw)
+    c = 1540.0
+    dt = cfl * h / c
+    grid = (n, n)
+    row = tissue_row(0.5, 1.1, 2, 2e6)
+    prob = Problem(shape=(n, n), h=h, dt=dt, n_relax=2,
+                   c=np.full(grid, c, np.float32), rho=np.full(grid, 1000.0, np.float32),
+                   beta=np.full(grid, 3.5, np.float32), relax_table=np.asarray([row]),
+                   bound_cells=(nb, nb), trans_cells=(ntr, ntr), n_steps=n_steps,
+                   name="plain_2d_%d" % n)
+    xs = np.arange(nb, nb + interior)
+    prob.src_idx = prob.flat(xs, np.full_like(xs, nb + 8))
+    prob.src_sig = np.zeros(xs.size, np.int32)
+    prob.src_w = np.ones(xs.size, np.float32)
+    nt = pulse_length(dt, f0, 3)
+    prob.signals = gaussian_pulse(nt, dt, f0, 3, amp=1e5)[None, :]
+    rx = np.round(np.linspace(nb, nb + interior - 1, n_rcv)).astype(np.int64)
+    ry = min(nb + 300, n - nb - 1)
+    prob.rcv_idx = prob.flat(rx, np.full_like(rx, ry))
+    return prob
+
+
+# ---------------------------------------------------------------------------
+# Workload 2: heterogeneous abdominal-wall-like 2D medium, L = 4
+# ---------------------------------------------------------------------------
+
+def abdominal_2d(nx=4096, ny=2048, seed=2, n_steps=12000, ppw=12, f0=3e6, cfl=0.4,
+                 n_interfaces=8, n_scatter=100000, n_elem=128, L=4):
+    """Layered fat/muscle/connective medium with undulating interfaces and
+    single-cell sound-speed scatterers; a linear array transmits a plane wave
+    (zero delays) and receives on its element centres.  nx is the lateral
+    (fastest) axis, ny the depth.  Smaller nx, ny give the same recipe on a
+    smaller grid (parity tests)."""
+    rng = np.random.default_rng(seed)
+    lam = ppw
+    nb, ntr = 4 * lam, 3 * lam
+    h = grid_spacing(1540.0, f0, ppw)
+    grid = (ny, nx)
+    W = nx * h
+    depth = (ny - 2 * nb) * h
+    # interfaces: y_k(x) = y_k0 + sum_m A_m sin(2 pi m x / W + phi_m), A <= 1 mm
+    x = np.arange(nx) * h
+    y0 = np.sort(rng.uniform(0.05, 0.95, n_interfaces)) * depth + nb * h
+    ifc = np.empty((n_interfaces, nx))
+    for k in range(n_interfaces):
+        amp = rng.uniform(0.0, 1e-3, 3)
+        ph = rng.uniform(0, 2 * np.pi, 3)
+        ifc[k] = y0[k] + sum(amp[m] * np.sin(2 * np.pi * (m + 1) * x / W + ph[m]) for m in range(3))
+    yy = (np.arange(ny) * h)[:, None]
+    layer = np.zeros(grid, np.int32)
+    for k in range(n_interfaces):
+        layer += (yy >= ifc[k][None, :]).astype(np.int32)
+    n_layers = n_interfaces + 1
+    # per-layer tissue class and properties
+    classes = rng.integers(0, 3, n_layers)     # 0 fat, 1 muscle, 2 connective
+    c_l = rng.uniform(1450.0, 1620.0, n_layers)
+    rho_l = rng.uniform(950.0, 1120.0, n_layers)
+    beta_l = rng.uniform(3.5, 5.5, n_layers)
+    a0_l = [ALPHA0_GRID[i] for i in rng.integers(0, len(ALPHA0_GRID), n_layers)]
+    y_l = [Y_GRID[i] for i in rng.integers(0, len(Y_GRID), n_layers)]
+    rows = [tissue_row(a0_l[k], y_l[k], L, 3e6) for k in range(n_layers)]
+    c = c_l[layer].astype(np.float32)
+    rho = rho_l[layer].astype(np.float32)
+    beta = beta_l[layer].astype(np.float32)
+    label = layer.astype(np.uint8)
+    # sub-resolution scatterers: single cells (< lambda/10 in size), c * (1 + 0.02 N(0,1))
+    n_sc = int(min(n_scatter, nx * ny // 16))
+    sx = rng.integers(0, nx, n_sc)
+    sy = rng.integers(0, ny, n_sc)
+    c[sy, sx] = (c[sy, sx] * (1.0 + 0.02 * rng.standard_normal(n_sc))).astype(np.float32)
+    dt = cfl * h / float(c.max())
+    prob = Problem(shape=(nx, ny), h=h, dt=dt, n_relax=L, c=c, rho=rho, beta=beta,
+                   relax_table=np.asarray(rows, np.float64), label=label,
+                   bound_cells=(nb, nb), trans_cells=(ntr, ntr), n_steps=n_steps,
+                   name="abdominal_2d_%dx%d" % (nx, ny))
+    prob.meta = {"classes": classes.tolist(), "alpha0": a0_l, "y": y_l}
+    # linear array: pitch 12 cells (~ lambda), element width 10 cells, 8 cells
+    # below the top boundary layer; fewer elements if the grid is narrow
+    pitch, width = 12, 10
+    n_el = int(min(n_elem, (nx - 2 * nb) // pitch))
+    x0 = nx // 2 - (n_el * pitch) // 2
+    ey = nb + 8
+    ex = np.concatenate([x0 + e * pitch + np.arange(width) for e in range(n_el)])
+    prob.src_idx = prob.flat(ex, np.full_like(ex, ey))
+    prob.src_sig = np.repeat(np.arange(n_el, dtype=np.int32), width)
+    prob.src_w = np.ones(ex.size, np.float32)
+    nt = pulse_length(dt, f0, 3)
+    pulse = gaussian_pulse(nt, dt, f0, 3, amp=1e5)
+    prob.signals = np.repeat(pulse[None, :], n_el, axis=0)   # plane wave: zero delays
+    centres = x0 + np.arange(n_el) * pitch + width // 2
+    prob.rcv_idx = prob.flat(centres, np.full_like(centres, ey))
+    return prob
