@@ -1,0 +1,176 @@
+/*
+ * fw2.h -- C ABI of libfw2, the gfx950 time stepper of the Fullwave 2 system
+ * (Sode & Pinton, arXiv 2106.11476): the first-order nonlinear acoustic
+ * equations with coordinate-stretched derivatives (Sec. 2.2, Eqs. general5 and
+ * general6) on a staggered grid with the (8,4) stencil (Sec. 3.1), memory
+ * variables for L relaxation mechanisms (Sec. 3.2) and the two-stage C-PML
+ * with its transition layer (Sec. 3.3, Table 1).
+ *
+ * Conventions
+ *   - Grids are x fastest: flat index = x + nx * (y + ny * z); nz = 1 in 2D.
+ *   - Pressure p sits at integer positions; v_a (a = x, y, z) sits half a cell
+ *     along a.  The v_a sample past the last pressure sample along a lies
+ *     outside the grid and is held at zero.  Fields outside the grid are zero.
+ *   - All device arithmetic is FP32; derived coefficients are computed in FP64
+ *     on the host during fw2_create_domain.
+ *   - Every call returns fw2_status; nothing throws across the ABI.  On error
+ *     fw2_last_error() returns a message for the calling thread.
+ *   - A domain is not thread-safe; distinct domains may be used from
+ *     different threads and streams at the same time.
+ */
+#ifndef FW2_H
+#define FW2_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fw2_domain fw2_domain;
+
+typedef enum {
+    FW2_OK = 0,
+    FW2_E_INVALID = 1,      /* bad argument; nothing was changed */
+    FW2_E_NOMEM = 2,        /* workspace too small or host allocation failed */
+    FW2_E_HIP = 3,          /* a HIP runtime call failed */
+    FW2_E_STATE = 4,        /* call not valid in the domain's current state */
+    FW2_E_UNSTABLE = 5,     /* watchdog found a non-finite or runaway field */
+    FW2_E_UNSUPPORTED = 6   /* valid request this build does not implement */
+} fw2_status;
+
+#define FW2_MAX_RELAX 4     /* largest number of relaxation mechanisms L */
+#define FW2_MAX_LABELS 256  /* relaxation tuples addressable by a uint8 label */
+
+/* Field selection for fw2_read_fields / fw2_write_fields.  Selected fields
+ * are packed in this order, each as FP32 [nz][ny][nx] arrays:
+ *   P: p;  V: v_x, v_y[, v_z];  PSI1: psi1[axis][mechanism] (nabla_1 memory
+ *   variables, at the v points);  PSI2: psi2[axis][mechanism] (nabla_2, at the
+ *   p points). */
+enum {
+    FW2_FIELD_P = 1u,
+    FW2_FIELD_V = 2u,
+    FW2_FIELD_PSI1 = 4u,
+    FW2_FIELD_PSI2 = 8u,
+    FW2_FIELD_ALL = 15u
+};
+
+/* Memory pointer kinds. */
+enum { FW2_HOST = 0, FW2_DEVICE = 1 };
+
+/* Evaluation of the memory variables (Sec. 3.2).
+ *   FW2_RELAX_PRINTED: Eq. relaxation_psi as printed, psi^n = b psi^{n-1} +
+ *     a D^{n-1/2}, the updated psi used in the same step.
+ *   FW2_RELAX_CENTRED: the same exponential convolution evaluated at the time
+ *     of the newest derivative sample, with the derivative linear between
+ *     samples; same state and cost, and it reproduces the dispersion relation
+ *     (Eq. dispersion_relations), which the printed form misses by about a
+ *     fifth of the attenuation at 12 points per wavelength, CFL 0.4. */
+enum { FW2_RELAX_PRINTED = 0, FW2_RELAX_CENTRED = 1 };
+
+typedef struct {
+    int32_t ndim;             /* 2 or 3 */
+    int32_t n_relax;          /* L, 1..FW2_MAX_RELAX */
+    int64_t n[3];             /* nx, ny, nz including the boundary layers; nz = 1 in 2D */
+    double h;                 /* grid step (m) */
+    double dt;                /* time step (s) */
+    int32_t bound_cells[3];   /* L_C-PML per side per axis, in cells (Sec. 3.3) */
+    int32_t trans_cells[3];   /* L_Transition per side per axis, 0..bound_cells */
+    double pml_Rc;            /* R_c of Table 1's d target, 0 < R_c < 1 */
+    int32_t pml_npoly;        /* polynomial order N of Eq. polynomial_transition, >= 1 */
+    double pml_cp;            /* c_p of Table 1's d target; <= 0: largest c of the map */
+    double fd_r;              /* Courant number of the (8,4) weights; <= 0: max(c) dt / h */
+    int32_t relax_scheme;     /* FW2_RELAX_PRINTED or FW2_RELAX_CENTRED */
+    const float *c;           /* host [nz][ny][nx] sound speed (m/s), > 0 */
+    const float *rho;         /* host [nz][ny][nx] equilibrium density rho_0 (kg/m^3), > 0 */
+    const float *beta;        /* host [nz][ny][nx] coefficient of nonlinearity 1 + B/2A */
+    const uint8_t *label;     /* host [nz][ny][nx] relaxation-tuple index, or NULL (all 0) */
+    int32_t n_labels;         /* rows of relax_table, 1..FW2_MAX_LABELS */
+    const double *relax_table;/* host [n_labels][2 + 4L]: k1, k2, d1[L], d2[L], alpha1[L],
+                                 alpha2[L] -- the 2 + 4L isotropic parameters of Sec. 3.2 */
+    void *stream;             /* hipStream_t for all work of the domain; NULL = null stream */
+} fw2_domain_desc;
+
+/* Bytes of device workspace a domain described by desc needs (host-only
+ * computation; validates desc).  Returns FW2_E_INVALID for a bad desc. */
+fw2_status fw2_workspace_bytes(const fw2_domain_desc *desc, uint64_t *bytes);
+
+/* Create a domain (Sec. 3 setup: stencil weights from r, per-tissue and
+ * per-boundary-position memory coefficients from Eqs. relaxation_a / _b and
+ * Table 1's profiles, medium values from c, rho, beta).
+ *   dev_workspace: caller-owned device buffer of at least fw2_workspace_bytes,
+ *     256-byte aligned; it must outlive the domain.  The library performs no
+ *     device allocation of its own beyond HIP events and graphs.
+ *   The host maps are read during the call and may be freed afterwards.
+ *   All fields start at zero; the step counter starts at 0.
+ *   Rejects a time step above the scheme's stability limit (FW2_E_INVALID). */
+fw2_status fw2_create_domain(const fw2_domain_desc *desc, void *dev_workspace,
+                             uint64_t workspace_bytes, fw2_domain **out);
+
+/* Additive pressure sources (reading of the source model: the paper names the
+ * pulse, not the injection).  After the pressure update of step k (0-based),
+ * p[flat_idx[q]] += weight[q] * signals[sig_id[q]][k] for k < n_t.
+ *   flat_idx, sig_id, weight, signals: caller-owned DEVICE arrays that must
+ *     stay valid while the domain steps; flat indices must be distinct and in
+ *     range, sig_id in [0, n_sig) (checked here with a device-to-host copy).
+ *   A call replaces the previous source set; n_pts = 0 removes all sources. */
+fw2_status fw2_add_source(fw2_domain *dom, int32_t n_pts, const int64_t *flat_idx,
+                          const int32_t *sig_id, const float *weight, int32_t n_sig,
+                          int32_t n_t, const float *signals);
+
+/* Pressure receivers: after the sources of step k, trace[k][r] = p[flat_idx[r]]
+ * for k < cap_steps (rows are global step indices).
+ *   flat_idx and trace: caller-owned DEVICE arrays, trace is [cap_steps][n_rcv]
+ *   FP32.  A call replaces the previous receiver set; n_rcv = 0 removes it. */
+fw2_status fw2_add_receivers(fw2_domain *dom, int32_t n_rcv, const int64_t *flat_idx,
+                             float *trace, int64_t cap_steps);
+
+/* Advance n >= 0 steps, asynchronously on the domain's stream.  One step is
+ * the pressure phase, sources, receivers, then the velocity phase (Sec. 3.1
+ * leapfrog).  After fw2_step(n) from a zero state p is at t = n dt and v at
+ * (n + 1/2) dt. */
+fw2_status fw2_step(fw2_domain *dom, int32_t n);
+
+/* Copy the selected fields (order of the FW2_FIELD_ enum) into dst, packed,
+ * unpadded FP32.  dst_kind FW2_HOST or FW2_DEVICE.  Synchronises the stream. */
+fw2_status fw2_read_fields(fw2_domain *dom, uint32_t field_mask, void *dst, int32_t dst_kind);
+
+/* Overwrite the selected fields from src (same packing); for checkpoint and
+ * resume.  Values at v samples outside the grid are ignored (kept zero).
+ * Synchronises the stream. */
+fw2_status fw2_write_fields(fw2_domain *dom, uint32_t field_mask, const void *src, int32_t src_kind);
+
+/* Global index of the next step (sources and receivers use it). */
+int64_t fw2_current_step(const fw2_domain *dom);
+
+/* Set the global step index (resume from a checkpoint).  Synchronises. */
+fw2_status fw2_set_current_step(fw2_domain *dom, int64_t step);
+
+/* Steps captured per HIP graph replay (0 disables graphs; default 32).
+ * Graph and direct launches give bitwise identical results. */
+fw2_status fw2_set_graph_chunk(fw2_domain *dom, int32_t steps);
+
+/* Per-kernel HIP-event timing on the domain's stream.  While enabled, steps
+ * are launched directly (no graphs) with events around the pressure and
+ * velocity kernels.  fw2_get_kernel_timing synchronises and returns the total
+ * milliseconds and launch counts since timing was enabled:
+ * index 0 = pressure kernel, 1 = velocity kernel. */
+fw2_status fw2_enable_kernel_timing(fw2_domain *dom, int32_t enable);
+fw2_status fw2_get_kernel_timing(fw2_domain *dom, double ms[2], int64_t count[2]);
+
+/* Watchdog: synchronises and checks that every pressure sample is finite and
+ * below limit in magnitude; FW2_E_UNSTABLE otherwise. */
+fw2_status fw2_check_finite(fw2_domain *dom, float limit);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *fw2_last_error(void);
+
+/* Free host-side state (events, graphs).  Does not touch the workspace,
+ * sources or traces, which the caller owns.  NULL is a no-op. */
+void fw2_destroy_domain(fw2_domain *dom);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FW2_H */

@@ -1,0 +1,641 @@
+// libfw2: C ABI (include/fw2.h) around the gfx950 step kernels.
+#include "fw2.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+#include "setup.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+fw2_status fail(fw2_status st, const std::string &msg)
+{
+    g_err = msg;
+    return st;
+}
+
+#define FW2_HIP(call)                                                                     \
+    do {                                                                                  \
+        hipError_t e_ = (call);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return fail(FW2_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_));   \
+    } while (0)
+
+constexpr uint64_t kAlign = 256;
+constexpr int kTimingRing = 256;
+
+uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
+
+struct Layout {
+    fw2::Geometry geo;
+    int n_float;               // float arrays
+    uint64_t float_base;       // byte offset of array 0 (x = 0 lands 256-byte aligned)
+    uint64_t label_off;        // 0 if no label array
+    uint64_t tab_off[2][3];    // [nabla-1][axis] (b, c) tables
+    uint64_t w_off[2][3];      // [nabla-1][axis] w tables
+    int n_slots[2][3];
+    uint64_t total;
+};
+
+bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+// Everything that can be checked without reading the maps.
+fw2_status validate_scalars(const fw2_domain_desc *d)
+{
+    if (!d) return fail(FW2_E_INVALID, "desc is NULL");
+    if (d->ndim != 2 && d->ndim != 3) return fail(FW2_E_INVALID, "ndim must be 2 or 3");
+    if (d->n_relax < 1 || d->n_relax > FW2_MAX_RELAX)
+        return fail(FW2_E_INVALID, "n_relax must be in 1..4");
+    for (int a = 0; a < 3; ++a) {
+        const int64_t na = d->n[a];
+        if (a < d->ndim) {
+            if (na < 1 || na > (1 << 20)) return fail(FW2_E_INVALID, "grid size out of range");
+            if (d->bound_cells[a] < 0 || d->trans_cells[a] < 0 || d->trans_cells[a] > d->bound_cells[a])
+                return fail(FW2_E_INVALID, "need 0 <= trans_cells <= bound_cells");
+            if (2 * (int64_t)d->bound_cells[a] > na)
+                return fail(FW2_E_INVALID, "boundary layers wider than the grid");
+        } else if (na != 1) {
+            return fail(FW2_E_INVALID, "n[2] must be 1 in 2D");
+        }
+    }
+    if (!finite_pos(d->h) || !finite_pos(d->dt)) return fail(FW2_E_INVALID, "h and dt must be positive");
+    if (!(d->pml_Rc > 0.0 && d->pml_Rc < 1.0)) return fail(FW2_E_INVALID, "pml_Rc must be in (0, 1)");
+    if (d->pml_npoly < 1 || d->pml_npoly > 8) return fail(FW2_E_INVALID, "pml_npoly must be in 1..8");
+    if (!std::isfinite(d->pml_cp) || !std::isfinite(d->fd_r)) return fail(FW2_E_INVALID, "non-finite pml_cp/fd_r");
+    if (d->relax_scheme != FW2_RELAX_PRINTED && d->relax_scheme != FW2_RELAX_CENTRED)
+        return fail(FW2_E_INVALID, "relax_scheme must be 0 or 1");
+    if (d->n_labels < 1 || d->n_labels > FW2_MAX_LABELS) return fail(FW2_E_INVALID, "n_labels must be in 1..256");
+    if (!d->c || !d->rho || !d->beta || !d->relax_table) return fail(FW2_E_INVALID, "NULL map or table");
+    const int L = d->n_relax, row = 2 + 4 * L;
+    for (int lab = 0; lab < d->n_labels; ++lab) {
+        const double *r = d->relax_table + (size_t)lab * row;
+        if (!finite_pos(r[0]) || !finite_pos(r[1])) return fail(FW2_E_INVALID, "kappa must be positive");
+        for (int q = 2; q < row; ++q)
+            if (!std::isfinite(r[q]) || r[q] < 0.0) return fail(FW2_E_INVALID, "d and alpha must be >= 0");
+    }
+    return FW2_OK;
+}
+
+void make_layout(const fw2_domain_desc *d, Layout *ly)
+{
+    fw2::Geometry &g = ly->geo;
+    g.ndim = d->ndim;
+    for (int a = 0; a < 3; ++a) g.n[a] = (int32_t)d->n[a];
+    const int64_t H = fw2::kHalo;
+    g.pitch = (int64_t)align_up((uint64_t)(g.n[0] + 2 * H), 64);
+    g.plane = g.pitch * (g.n[1] + 2 * H);
+    const int64_t planes = d->ndim == 3 ? g.n[2] + 2 * H : 1;
+    g.stride = g.plane * planes;                           // multiple of 64 elements
+    g.origin = (d->ndim == 3 ? H * g.plane : 0) + H * g.pitch + H;
+    const int L = d->n_relax;
+    ly->n_float = 1 + d->ndim + 2 * d->ndim * L + 3;
+    ly->float_base = kAlign + kAlign - (uint64_t)(H * 4) % kAlign;   // x = 0 on a 256-byte boundary
+    uint64_t end = ly->float_base + (uint64_t)ly->n_float * g.stride * 4;
+    end = align_up(end, kAlign);
+    ly->label_off = 0;
+    if (d->n_labels > 1) {
+        ly->label_off = end;
+        end = align_up(end + (uint64_t)g.stride, kAlign);
+    }
+    for (int nab = 0; nab < 2; ++nab)
+        for (int a = 0; a < 3; ++a) {
+            if (a >= d->ndim) {
+                ly->n_slots[nab][a] = 0;
+                ly->tab_off[nab][a] = ly->w_off[nab][a] = 0;
+                continue;
+            }
+            const int nb = d->bound_cells[a];
+            const int ns = nab == 0 ? nb + 2 : nb + 1;     // nabla_1: half positions
+            ly->n_slots[nab][a] = ns;
+            ly->tab_off[nab][a] = end;
+            end = align_up(end + (uint64_t)ns * d->n_labels * L * 8, kAlign);
+            ly->w_off[nab][a] = end;
+            end = align_up(end + (uint64_t)ns * d->n_labels * 4, kAlign);
+        }
+    ly->total = end;
+}
+
+double max_c(const fw2_domain_desc *d, int64_t npts)
+{
+    double m = 0.0;
+    for (int64_t q = 0; q < npts; ++q) m = std::max(m, (double)d->c[q]);
+    return m;
+}
+
+struct TimingSlot {
+    hipEvent_t ev[4];
+    bool pending;
+};
+
+}  // namespace
+
+struct fw2_domain {
+    fw2_domain_desc desc;      // scalars only (host pointers cleared)
+    Layout ly;
+    uint8_t *ws = nullptr;
+    long long *counter = nullptr;
+    int *flag = nullptr;
+    fw2::StepArgs args;
+    fw2::SparseArgs src, rcv;
+    hipStream_t stream = nullptr;
+    hipStream_t capture = nullptr;
+    int64_t step = 0;
+    int graph_chunk = 32;
+    hipGraphExec_t graph = nullptr;
+    bool timing = false;
+    std::vector<TimingSlot> ring;
+    int64_t timed_steps = 0;
+    double ms[2] = {0.0, 0.0};
+    int64_t count[2] = {0, 0};
+    int64_t npts() const { return (int64_t)ly.geo.n[0] * ly.geo.n[1] * ly.geo.n[2]; }
+};
+
+namespace {
+
+void drop_graph(fw2_domain *d)
+{
+    if (d->graph) {
+        (void)hipGraphExecDestroy(d->graph);
+        d->graph = nullptr;
+    }
+}
+
+fw2_status enqueue_step(fw2_domain *d, TimingSlot *ts)
+{
+    const int L = d->desc.n_relax, sch = d->desc.relax_scheme;
+    if (ts) FW2_HIP(hipEventRecord(ts->ev[0], d->stream));
+    FW2_HIP(fw2::launch_pressure(d->args, L, sch, d->stream));
+    if (ts) FW2_HIP(hipEventRecord(ts->ev[1], d->stream));
+    FW2_HIP(fw2::launch_sources(d->src, d->stream));
+    FW2_HIP(fw2::launch_receivers(d->rcv, d->stream));
+    if (ts) FW2_HIP(hipEventRecord(ts->ev[2], d->stream));
+    FW2_HIP(fw2::launch_velocity(d->args, L, sch, d->stream));
+    if (ts) FW2_HIP(hipEventRecord(ts->ev[3], d->stream));
+    return FW2_OK;
+}
+
+fw2_status enqueue_step_on(fw2_domain *d, hipStream_t s)
+{
+    const int L = d->desc.n_relax, sch = d->desc.relax_scheme;
+    FW2_HIP(fw2::launch_pressure(d->args, L, sch, s));
+    FW2_HIP(fw2::launch_sources(d->src, s));
+    FW2_HIP(fw2::launch_receivers(d->rcv, s));
+    FW2_HIP(fw2::launch_velocity(d->args, L, sch, s));
+    return FW2_OK;
+}
+
+fw2_status build_graph(fw2_domain *d)
+{
+    if (!d->capture) FW2_HIP(hipStreamCreateWithFlags(&d->capture, hipStreamNonBlocking));
+    FW2_HIP(hipStreamBeginCapture(d->capture, hipStreamCaptureModeThreadLocal));
+    fw2_status st = FW2_OK;
+    for (int k = 0; k < d->graph_chunk && st == FW2_OK; ++k) st = enqueue_step_on(d, d->capture);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(d->capture, &graph);
+    if (st != FW2_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st;
+    }
+    if (e != hipSuccess) return fail(FW2_E_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(&d->graph, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+        d->graph = nullptr;
+        return fail(FW2_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    }
+    return FW2_OK;
+}
+
+fw2_status collect_slot(fw2_domain *d, TimingSlot &s)
+{
+    if (!s.pending) return FW2_OK;
+    FW2_HIP(hipEventSynchronize(s.ev[3]));
+    float a = 0.f, b = 0.f;
+    FW2_HIP(hipEventElapsedTime(&a, s.ev[0], s.ev[1]));
+    FW2_HIP(hipEventElapsedTime(&b, s.ev[2], s.ev[3]));
+    d->ms[0] += a;
+    d->ms[1] += b;
+    d->count[0] += 1;
+    d->count[1] += 1;
+    s.pending = false;
+    return FW2_OK;
+}
+
+// Copy between the packed [nz][ny][nx] layout and the padded device layout
+// for the sub-box [0, ext[0]) x [0, ext[1]) x [0, ext[2]).
+fw2_status copy_box(fw2_domain *d, float *dev_base, void *packed, bool to_device, hipMemcpyKind kind,
+                    const int ext[3])
+{
+    const fw2::Geometry &g = d->ly.geo;
+    const size_t row_b = (size_t)g.n[0] * 4;
+    for (int z = 0; z < ext[2]; ++z) {
+        float *dev = dev_base + g.origin + (int64_t)z * g.plane;
+        char *host = (char *)packed + (size_t)z * g.n[1] * row_b;
+        if (to_device)
+            FW2_HIP(hipMemcpy2DAsync(dev, (size_t)g.pitch * 4, host, row_b, (size_t)ext[0] * 4, ext[1], kind, d->stream));
+        else
+            FW2_HIP(hipMemcpy2DAsync(host, row_b, dev, (size_t)g.pitch * 4, (size_t)ext[0] * 4, ext[1], kind, d->stream));
+    }
+    return FW2_OK;
+}
+
+fw2_status transfer_fields(fw2_domain *d, uint32_t mask, void *buf, int32_t kind, bool to_device)
+{
+    if (!d) return fail(FW2_E_STATE, "domain is NULL");
+    if (!buf) return fail(FW2_E_INVALID, "buffer is NULL");
+    if (mask == 0 || (mask & ~FW2_FIELD_ALL)) return fail(FW2_E_INVALID, "bad field mask");
+    if (kind != FW2_HOST && kind != FW2_DEVICE) return fail(FW2_E_INVALID, "bad pointer kind");
+    const hipMemcpyKind k = kind == FW2_DEVICE ? hipMemcpyDeviceToDevice
+                                               : (to_device ? hipMemcpyHostToDevice : hipMemcpyDeviceToHost);
+    const fw2::Geometry &g = d->ly.geo;
+    const int nd = g.ndim, L = d->desc.n_relax;
+    const size_t field_b = (size_t)d->npts() * 4;
+    char *cur = (char *)buf;
+    FW2_HIP(hipStreamSynchronize(d->stream));
+    auto one = [&](float *base, int axis) -> fw2_status {
+        int ext[3] = {g.n[0], g.n[1], g.n[2]};
+        if (axis >= 0 && to_device) ext[axis] -= 1;      // v sample past the grid stays zero
+        if (axis >= 0 && to_device && ext[axis] == 0) {
+            cur += field_b;
+            return FW2_OK;
+        }
+        fw2_status st = copy_box(d, base, cur, to_device, k, ext);
+        cur += field_b;
+        return st;
+    };
+    fw2_status st = FW2_OK;
+    if (mask & FW2_FIELD_P) st = one(d->args.p, -1);
+    if (st == FW2_OK && (mask & FW2_FIELD_V))
+        for (int a = 0; a < nd && st == FW2_OK; ++a) st = one(d->args.v + a * g.stride, a);
+    if (st == FW2_OK && (mask & FW2_FIELD_PSI1))
+        for (int a = 0; a < nd; ++a)
+            for (int nu = 0; nu < L && st == FW2_OK; ++nu)
+                st = one(d->args.psi1 + (int64_t)(a * L + nu) * g.stride, a);
+    if (st == FW2_OK && (mask & FW2_FIELD_PSI2))
+        for (int a = 0; a < nd; ++a)
+            for (int nu = 0; nu < L && st == FW2_OK; ++nu)
+                st = one(d->args.psi2 + (int64_t)(a * L + nu) * g.stride, -1);
+    if (st != FW2_OK) return st;
+    FW2_HIP(hipStreamSynchronize(d->stream));
+    return FW2_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *fw2_last_error(void) { return g_err.c_str(); }
+
+fw2_status fw2_workspace_bytes(const fw2_domain_desc *desc, uint64_t *bytes)
+{
+    fw2_status st = validate_scalars(desc);
+    if (st != FW2_OK) return st;
+    if (!bytes) return fail(FW2_E_INVALID, "bytes is NULL");
+    Layout ly;
+    make_layout(desc, &ly);
+    *bytes = ly.total;
+    return FW2_OK;
+}
+
+fw2_status fw2_create_domain(const fw2_domain_desc *desc, void *dev_workspace, uint64_t workspace_bytes,
+                             fw2_domain **out)
+{
+    fw2_status st = validate_scalars(desc);
+    if (st != FW2_OK) return st;
+    if (!out) return fail(FW2_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!dev_workspace) return fail(FW2_E_INVALID, "workspace is NULL");
+    if ((uintptr_t)dev_workspace % kAlign) return fail(FW2_E_INVALID, "workspace must be 256-byte aligned");
+    Layout ly;
+    make_layout(desc, &ly);
+    if (workspace_bytes < ly.total) return fail(FW2_E_NOMEM, "workspace too small");
+
+    const fw2::Geometry &g = ly.geo;
+    const int nd = desc->ndim, L = desc->n_relax;
+    const int64_t npts = (int64_t)g.n[0] * g.n[1] * g.n[2];
+
+    // Map checks and the largest sound speed (stencil r, Table 1 c_p).
+    for (int64_t q = 0; q < npts; ++q) {
+        if (!finite_pos(desc->c[q]) || !finite_pos(desc->rho[q]) || !std::isfinite(desc->beta[q]))
+            return fail(FW2_E_INVALID, "c and rho must be positive and finite, beta finite");
+        if (desc->label && desc->label[q] >= desc->n_labels) return fail(FW2_E_INVALID, "label >= n_labels");
+    }
+    const double cmax = max_c(desc, npts);
+    const double r = desc->fd_r > 0.0 ? desc->fd_r : cmax * desc->dt / desc->h;
+    double gw[4], g11;
+    fw2::stencil_weights(r, nd, gw, &g11);
+    const double r_run = cmax * desc->dt / desc->h;
+    if (fw2::stability_factor(r_run, nd, gw, g11) >= 1.0)
+        return fail(FW2_E_INVALID, "time step above the stability limit of the (8,4) scheme");
+
+    fw2_domain *d = new (std::nothrow) fw2_domain();
+    if (!d) return fail(FW2_E_NOMEM, "host allocation failed");
+    d->desc = *desc;
+    d->desc.c = d->desc.rho = d->desc.beta = nullptr;
+    d->desc.label = nullptr;
+    d->desc.relax_table = nullptr;
+    d->ly = ly;
+    d->ws = (uint8_t *)dev_workspace;
+    d->stream = (hipStream_t)desc->stream;
+    d->counter = (long long *)d->ws;
+    d->flag = (int *)(d->ws + 8);
+
+    auto cleanup = [&](fw2_status s) {
+        delete d;
+        return s;
+    };
+#define FW2_HIP_C(call)                                                                              \
+    do {                                                                                             \
+        hipError_t e_ = (call);                                                                      \
+        if (e_ != hipSuccess) return cleanup(fail(FW2_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_))); \
+    } while (0)
+
+    FW2_HIP_C(hipMemsetAsync(d->ws, 0, ly.total, d->stream));
+    FW2_HIP_C(hipStreamSynchronize(d->stream));     // the uploads below use blocking copies
+
+    float *fb = (float *)(d->ws + ly.float_base);
+    fw2::StepArgs &a = d->args;
+    a.geo = g;
+    a.p = fb;
+    a.v = fb + g.stride;
+    a.psi1 = fb + (1 + nd) * g.stride;
+    a.psi2 = a.psi1 + (int64_t)nd * L * g.stride;
+    float *kap = a.psi2 + (int64_t)nd * L * g.stride;
+    float *nlq = kap + g.stride;
+    float *rho = nlq + g.stride;
+    a.kap = kap;
+    a.nlq = nlq;
+    a.rho = rho;
+    a.label = ly.label_off ? d->ws + ly.label_off : nullptr;
+    a.n_labels = desc->n_labels;
+    for (int k = 0; k < 4; ++k) a.g[k] = (float)(gw[k] / desc->h);
+    a.g11 = (float)(g11 / desc->h);
+    a.dt = (float)desc->dt;
+
+    // Medium planes: kappa0 = 1/(rho c^2), kappa0 (1 - 2 beta), rho (FP64, stored FP32).
+    {
+        const size_t plane_n = (size_t)g.plane;
+        std::vector<float> hk(plane_n, 0.f), hn(plane_n, 0.f), hr(plane_n, 0.f);
+        std::vector<uint8_t> hl(a.label ? plane_n : 0, 0);
+        const int64_t z0 = nd == 3 ? fw2::kHalo : 0;
+        for (int z = 0; z < g.n[2]; ++z) {
+            for (int y = 0; y < g.n[1]; ++y)
+                for (int x = 0; x < g.n[0]; ++x) {
+                    const int64_t q = ((int64_t)z * g.n[1] + y) * g.n[0] + x;
+                    const size_t o = (size_t)(y + fw2::kHalo) * g.pitch + x + fw2::kHalo;
+                    const double c = desc->c[q], rr = desc->rho[q], b = desc->beta[q];
+                    const double k0 = 1.0 / (rr * c * c);
+                    hk[o] = (float)k0;
+                    hn[o] = (float)(k0 * (1.0 - 2.0 * b));
+                    hr[o] = (float)rr;
+                    if (a.label) hl[o] = desc->label[q];
+                }
+            const int64_t off = (z + z0) * g.plane;
+            FW2_HIP_C(hipMemcpy(kap + off, hk.data(), plane_n * 4, hipMemcpyHostToDevice));
+            FW2_HIP_C(hipMemcpy(nlq + off, hn.data(), plane_n * 4, hipMemcpyHostToDevice));
+            FW2_HIP_C(hipMemcpy(rho + off, hr.data(), plane_n * 4, hipMemcpyHostToDevice));
+            if (a.label)
+                FW2_HIP_C(hipMemcpy((uint8_t *)a.label + off, hl.data(), plane_n, hipMemcpyHostToDevice));
+        }
+    }
+
+    // Relaxation tables per axis (Sec. 3.2, Sec. 3.3 / Table 1).
+    const double cp = desc->pml_cp > 0.0 ? desc->pml_cp : cmax;
+    for (int ax = 0; ax < nd; ++ax) {
+        const int nb = desc->bound_cells[ax], ntr = desc->trans_cells[ax];
+        fw2::TableInput in;
+        in.n_labels = desc->n_labels;
+        in.L = L;
+        in.scheme = desc->relax_scheme;
+        in.table = desc->relax_table;
+        in.h = desc->h;
+        in.dt = desc->dt;
+        in.npoly = desc->pml_npoly;
+        in.d_target = nb > 0 ? -(desc->pml_npoly + 1) * cp * std::log(desc->pml_Rc) / (2.0 * nb * desc->h) : 0.0;
+        a.nb[ax] = nb;
+        for (int nab = 0; nab < 2; ++nab) {
+            const fw2::AxisTables t = fw2::build_axis_tables(in, nab + 1, nb, ntr);
+            float2 *bc = (float2 *)(d->ws + ly.tab_off[nab][ax]);
+            float *w = (float *)(d->ws + ly.w_off[nab][ax]);
+            FW2_HIP_C(hipMemcpy(bc, t.bc.data(), t.bc.size() * 4, hipMemcpyHostToDevice));
+            FW2_HIP_C(hipMemcpy(w, t.w.data(), t.w.size() * 4, hipMemcpyHostToDevice));
+            if (nab == 0) {
+                a.bc1[ax] = bc;
+                a.w1[ax] = w;
+            } else {
+                a.bc2[ax] = bc;
+                a.w2[ax] = w;
+            }
+        }
+    }
+    for (int ax = nd; ax < 3; ++ax) {
+        a.nb[ax] = 0;
+        a.bc1[ax] = a.bc2[ax] = nullptr;
+        a.w1[ax] = a.w2[ax] = nullptr;
+    }
+
+    std::memset(&d->src, 0, sizeof(d->src));
+    std::memset(&d->rcv, 0, sizeof(d->rcv));
+    d->src.geo = d->rcv.geo = g;
+    d->src.p = d->rcv.p = a.p;
+    d->src.step = d->rcv.step = d->counter;
+    FW2_HIP_C(hipStreamSynchronize(d->stream));
+#undef FW2_HIP_C
+    *out = d;
+    return FW2_OK;
+}
+
+fw2_status fw2_add_source(fw2_domain *d, int32_t n_pts, const int64_t *flat_idx, const int32_t *sig_id,
+                          const float *weight, int32_t n_sig, int32_t n_t, const float *signals)
+{
+    if (!d) return fail(FW2_E_STATE, "domain is NULL");
+    if (n_pts < 0) return fail(FW2_E_INVALID, "n_pts < 0");
+    if (n_pts > 0) {
+        if (!flat_idx || !sig_id || !weight || !signals) return fail(FW2_E_INVALID, "NULL source array");
+        if (n_sig < 1 || n_t < 1) return fail(FW2_E_INVALID, "need n_sig >= 1 and n_t >= 1");
+        std::vector<int64_t> hi(n_pts);
+        std::vector<int32_t> hs(n_pts);
+        FW2_HIP(hipMemcpy(hi.data(), flat_idx, (size_t)n_pts * 8, hipMemcpyDeviceToHost));
+        FW2_HIP(hipMemcpy(hs.data(), sig_id, (size_t)n_pts * 4, hipMemcpyDeviceToHost));
+        const int64_t np = d->npts();
+        for (int32_t q = 0; q < n_pts; ++q) {
+            if (hi[q] < 0 || hi[q] >= np) return fail(FW2_E_INVALID, "source index out of range");
+            if (hs[q] < 0 || hs[q] >= n_sig) return fail(FW2_E_INVALID, "sig_id out of range");
+        }
+        std::sort(hi.begin(), hi.end());
+        if (std::adjacent_find(hi.begin(), hi.end()) != hi.end())
+            return fail(FW2_E_INVALID, "source indices must be distinct");
+    }
+    drop_graph(d);
+    d->src.n = n_pts;
+    d->src.idx = flat_idx;
+    d->src.sig = sig_id;
+    d->src.w = weight;
+    d->src.signals = signals;
+    d->src.n_t = n_t;
+    return FW2_OK;
+}
+
+fw2_status fw2_add_receivers(fw2_domain *d, int32_t n_rcv, const int64_t *flat_idx, float *trace,
+                             int64_t cap_steps)
+{
+    if (!d) return fail(FW2_E_STATE, "domain is NULL");
+    if (n_rcv < 0 || cap_steps < 0) return fail(FW2_E_INVALID, "negative size");
+    if (n_rcv > 0) {
+        if (!flat_idx || !trace) return fail(FW2_E_INVALID, "NULL receiver array");
+        std::vector<int64_t> hi(n_rcv);
+        FW2_HIP(hipMemcpy(hi.data(), flat_idx, (size_t)n_rcv * 8, hipMemcpyDeviceToHost));
+        for (int64_t v : hi)
+            if (v < 0 || v >= d->npts()) return fail(FW2_E_INVALID, "receiver index out of range");
+    }
+    drop_graph(d);
+    d->rcv.n = n_rcv;
+    d->rcv.idx = flat_idx;
+    d->rcv.trace = trace;
+    d->rcv.cap = n_rcv > 0 ? cap_steps : 0;
+    return FW2_OK;
+}
+
+fw2_status fw2_step(fw2_domain *d, int32_t n)
+{
+    if (!d) return fail(FW2_E_STATE, "domain is NULL");
+    if (n < 0) return fail(FW2_E_INVALID, "n < 0");
+    if (n == 0) return FW2_OK;
+    if (d->timing) {
+        for (int32_t s = 0; s < n; ++s) {
+            TimingSlot &ts = d->ring[(size_t)(d->timed_steps % kTimingRing)];
+            fw2_status st = collect_slot(d, ts);
+            if (st != FW2_OK) return st;
+            st = enqueue_step(d, &ts);
+            if (st != FW2_OK) return st;
+            ts.pending = true;
+            d->timed_steps++;
+            d->step++;
+        }
+        return FW2_OK;
+    }
+    int32_t left = n;
+    if (d->graph_chunk > 0 && n >= d->graph_chunk) {
+        if (!d->graph) {
+            fw2_status st = build_graph(d);
+            if (st != FW2_OK) return st;
+        }
+        while (left >= d->graph_chunk) {
+            FW2_HIP(hipGraphLaunch(d->graph, d->stream));
+            left -= d->graph_chunk;
+            d->step += d->graph_chunk;
+        }
+    }
+    for (; left > 0; --left) {
+        fw2_status st = enqueue_step(d, nullptr);
+        if (st != FW2_OK) return st;
+        d->step++;
+    }
+    return FW2_OK;
+}
+
+fw2_status fw2_read_fields(fw2_domain *d, uint32_t mask, void *dst, int32_t kind)
+{
+    return transfer_fields(d, mask, dst, kind, false);
+}
+
+fw2_status fw2_write_fields(fw2_domain *d, uint32_t mask, const void *src, int32_t kind)
+{
+    return transfer_fields(d, mask, const_cast<void *>(src), kind, true);
+}
+
+int64_t fw2_current_step(const fw2_domain *d) { return d ? d->step : -1; }
+
+fw2_status fw2_set_current_step(fw2_domain *d, int64_t step)
+{
+    if (!d) return fail(FW2_E_STATE, "domain is NULL");
+    if (step < 0) return fail(FW2_E_INVALID, "step < 0");
+    FW2_HIP(fw2::launch_set_counter(d->counter, step, d->stream));
+    FW2_HIP(hipStreamSynchronize(d->stream));
+    d->step = step;
+    return FW2_OK;
+}
+
+fw2_status fw2_set_graph_chunk(fw2_domain *d, int32_t steps)
+{
+    if (!d) return fail(FW2_E_STATE, "domain is NULL");
+    if (steps < 0 || steps > 4096) return fail(FW2_E_INVALID, "graph chunk must be in 0..4096");
+    if (steps != d->graph_chunk) drop_graph(d);
+    d->graph_chunk = steps;
+    return FW2_OK;
+}
+
+fw2_status fw2_enable_kernel_timing(fw2_domain *d, int32_t enable)
+{
+    if (!d) return fail(FW2_E_STATE, "domain is NULL");
+    if (enable && !d->timing) {
+        if (d->ring.empty()) {
+            d->ring.resize(kTimingRing);
+            for (auto &s : d->ring) {
+                for (auto &e : s.ev) FW2_HIP(hipEventCreate(&e));
+                s.pending = false;
+            }
+        }
+        d->ms[0] = d->ms[1] = 0.0;
+        d->count[0] = d->count[1] = 0;
+    }
+    if (!enable && d->timing)
+        for (auto &s : d->ring) {
+            fw2_status st = collect_slot(d, s);
+            if (st != FW2_OK) return st;
+        }
+    d->timing = enable != 0;
+    return FW2_OK;
+}
+
+fw2_status fw2_get_kernel_timing(fw2_domain *d, double ms[2], int64_t count[2])
+{
+    if (!d) return fail(FW2_E_STATE, "domain is NULL");
+    if (!ms || !count) return fail(FW2_E_INVALID, "NULL output");
+    FW2_HIP(hipStreamSynchronize(d->stream));
+    for (auto &s : d->ring) {
+        fw2_status st = collect_slot(d, s);
+        if (st != FW2_OK) return st;
+    }
+    ms[0] = d->ms[0];
+    ms[1] = d->ms[1];
+    count[0] = d->count[0];
+    count[1] = d->count[1];
+    return FW2_OK;
+}
+
+fw2_status fw2_check_finite(fw2_domain *d, float limit)
+{
+    if (!d) return fail(FW2_E_STATE, "domain is NULL");
+    if (!(limit > 0.0f)) return fail(FW2_E_INVALID, "limit must be positive");
+    FW2_HIP(hipMemsetAsync(d->flag, 0, sizeof(int), d->stream));
+    FW2_HIP(fw2::launch_check(d->args.p, d->ly.geo, limit, d->flag, d->stream));
+    int h = 0;
+    FW2_HIP(hipMemcpyAsync(&h, d->flag, sizeof(int), hipMemcpyDeviceToHost, d->stream));
+    FW2_HIP(hipStreamSynchronize(d->stream));
+    if (h) return fail(FW2_E_UNSTABLE, "pressure field is not finite or exceeds the limit");
+    return FW2_OK;
+}
+
+void fw2_destroy_domain(fw2_domain *d)
+{
+    if (!d) return;
+    if (d->stream) (void)hipStreamSynchronize(d->stream);
+    drop_graph(d);
+    if (d->capture) (void)hipStreamDestroy(d->capture);
+    for (auto &s : d->ring)
+        for (auto &e : s.ev) (void)hipEventDestroy(e);
+    delete d;
+}
+
+}  // extern "C"

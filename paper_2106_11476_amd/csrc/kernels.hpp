@@ -1,0 +1,72 @@
+// Device data layout and kernel launchers of libfw2.
+//
+// Every per-point array (fields, memory variables, medium, labels) uses one
+// padded layout: a 4-cell zero halo on each side of every axis, rows of
+// `pitch` elements (a multiple of 64, so rows start on 256-byte boundaries),
+// planes of `plane` = pitch * (ny + 8) elements (3D).  Element (x, y, z) is at
+// origin + z * plane + y * pitch + x, and the arrays are placed so that x = 0
+// of every row is 256-byte aligned.  The halo of p and v is never written, so
+// stencil taps read zero outside the grid without bounds checks.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace fw2 {
+
+constexpr int kHalo = 4;
+constexpr int kMaxRelax = 4;
+
+struct Geometry {
+    int32_t ndim;
+    int32_t n[3];            // nx, ny, nz (nz = 1 in 2D)
+    int64_t pitch, plane;    // element strides of y and z
+    int64_t origin;          // element offset of (0, 0, 0)
+    int64_t stride;          // elements between consecutive arrays
+};
+
+struct StepArgs {
+    Geometry geo;
+    float *p;
+    float *v;                // v_a = v + a * stride
+    float *psi1;             // psi1[a][nu] = psi1 + (a * L + nu) * stride
+    float *psi2;
+    const float *kap;        // kappa0 = 1 / (rho c^2)
+    const float *nlq;        // kappa0 (1 - 2 beta)
+    const float *rho;        // rho0
+    const uint8_t *label;    // nullptr: a single relaxation tuple
+    int32_t n_labels;
+    int32_t nb[3];           // boundary cells per axis
+    const float *w2[3];      // pressure-point tables per axis: [slot][label]
+    const float2 *bc2[3];    //   [slot][label][nu] (b, c)
+    const float *w1[3];      // velocity-point tables per axis
+    const float2 *bc1[3];
+    float g[4];              // g_m0 / h
+    float g11;               // g_11 / h
+    float dt;
+};
+
+struct SparseArgs {
+    Geometry geo;
+    float *p;
+    long long *step;         // device step counter
+    const int64_t *idx;      // flat unpadded indices
+    const int32_t *sig;      // sources: signal of each point
+    const float *w;          // sources: weight of each point
+    const float *signals;    // sources: [n_sig][n_t]
+    float *trace;            // receivers: [cap][n]
+    int32_t n;               // points
+    int32_t n_t;             // sources: samples per signal
+    long long cap;           // receivers: trace rows
+};
+
+// Launchers (kernels.hip).  All enqueue on `stream` and return the launch error.
+hipError_t launch_pressure(const StepArgs &a, int L, int scheme, hipStream_t stream);
+hipError_t launch_velocity(const StepArgs &a, int L, int scheme, hipStream_t stream);
+hipError_t launch_sources(const SparseArgs &s, hipStream_t stream);
+hipError_t launch_receivers(const SparseArgs &s, hipStream_t stream);   // also advances the counter
+hipError_t launch_fill(float *dst, int64_t n, float value, hipStream_t stream);
+hipError_t launch_check(const float *p, const Geometry &g, float limit, int *flag, hipStream_t stream);
+hipError_t launch_set_counter(long long *counter, long long value, hipStream_t stream);
+
+}  // namespace fw2

@@ -1,0 +1,151 @@
+// Host-side setup math of libfw2 (FP64).  See setup.hpp.
+#include "setup.hpp"
+
+#include <algorithm>
+#include <cmath>
+
+namespace fw2 {
+
+void stencil_weights(double r, int ndim, double g[4], double *g11)
+{
+    // Augmented 4x5 system, row k: sum_j (2j-1)^(2k-1) c_j = r^(2k-2).
+    double A[4][5];
+    for (int k = 0; k < 4; ++k) {
+        for (int j = 0; j < 4; ++j) A[k][j] = std::pow(2.0 * j + 1.0, 2.0 * k + 1.0);
+        A[k][4] = std::pow(r, 2.0 * k);
+    }
+    for (int col = 0; col < 4; ++col) {          // Gaussian elimination, partial pivoting
+        int piv = col;
+        for (int row = col + 1; row < 4; ++row)
+            if (std::fabs(A[row][col]) > std::fabs(A[piv][col])) piv = row;
+        if (piv != col)
+            for (int j = 0; j < 5; ++j) std::swap(A[col][j], A[piv][j]);
+        for (int row = col + 1; row < 4; ++row) {
+            const double f = A[row][col] / A[col][col];
+            for (int j = col; j < 5; ++j) A[row][j] -= f * A[col][j];
+        }
+    }
+    double c[4];
+    for (int row = 3; row >= 0; --row) {
+        double s = A[row][4];
+        for (int j = row + 1; j < 4; ++j) s -= A[row][j] * c[j];
+        c[row] = s / A[row][row];
+    }
+    *g11 = r * r / 24.0;
+    for (int j = 0; j < 4; ++j) g[j] = c[j];
+    g[0] = c[0] - 2.0 * (ndim - 1) * (*g11);
+}
+
+double stability_factor(double r, int ndim, const double g[4], double g11)
+{
+    const int M = ndim == 2 ? 181 : 61;
+    const double pi = 3.14159265358979323846;
+    double worst = 0.0;
+    int cnt[3] = {M, M, ndim == 3 ? M : 1};
+    for (int iz = 0; iz < cnt[2]; ++iz)
+        for (int iy = 0; iy < cnt[1]; ++iy)
+            for (int ix = 0; ix < cnt[0]; ++ix) {
+                const double th[3] = {pi * ix / (M - 1), pi * iy / (M - 1),
+                                      ndim == 3 ? pi * iz / (M - 1) : 0.0};
+                double s2 = 0.0;
+                for (int a = 0; a < ndim; ++a) {
+                    double A = 0.0;
+                    for (int m = 1; m <= 4; ++m) A += g[m - 1] * std::sin((2 * m - 1) * th[a] / 2.0);
+                    double cs = 0.0;
+                    for (int b = 0; b < ndim; ++b)
+                        if (b != a) cs += std::cos(th[b]);
+                    A += 2.0 * g11 * std::sin(th[a] / 2.0) * cs;
+                    s2 += A * A;
+                }
+                worst = std::max(worst, r * std::sqrt(s2));
+            }
+    return worst;
+}
+
+double boundary_distance(int64_t twice_x, int64_t n, int nb)
+{
+    const double x = 0.5 * (double)twice_x;
+    double s = std::max(0.0, std::max((double)nb - x, x - (double)(n - 1 - nb)));
+    return std::min(s, (double)nb);
+}
+
+void layer_profile(double s, double h, int nb, int ntr, double d0, double a0, int nu,
+                   double d_target, int npoly, double *d, double *alpha)
+{
+    if (nb == 0 || s <= 0.0) {
+        *d = d0;
+        *alpha = a0;
+        return;
+    }
+    if (nu == 1) {
+        const double u = s / nb;                              // x / L_C-PML
+        const double gp = std::pow(u, (double)npoly);         // polynomial transition
+        *d = (d_target - d0) * gp + d0;
+        *alpha = (0.0 - a0) * u + a0;                         // linear transition
+        return;
+    }
+    double gc = 0.0;                                          // no transition layer: keep
+    if (ntr > 0) {
+        const double u = std::min(s, (double)ntr) / ntr;
+        gc = 0.5 * (1.0 - std::cos(3.14159265358979323846 * u));   // cosine transition
+    }
+    *d = (0.0 - d0) * gc + d0;
+    *alpha = (0.0 - a0) * gc + a0;
+}
+
+MechCoef mech_coef(double kappa, double d, double alpha, double dt)
+{
+    MechCoef m{0.0, 1.0, 0.0, 0.0};
+    const double lam = d / kappa + alpha;
+    m.b = std::exp(-lam * dt);
+    if (d == 0.0) return m;                 // kernel vanishes: a = e0 = e1 = 0
+    m.a = d / (kappa * (d + kappa * alpha)) * (m.b - 1.0);
+    // e1 = -(d/kappa^2) int_0^dt tau exp(-lam tau) dtau / dt ; e0 = a - e1
+    const double x = lam * dt;
+    const double amp = -d / (kappa * kappa);
+    const double i1 = (-std::expm1(-x) - x * std::exp(-x)) / (lam * x);
+    m.e1 = amp * i1;
+    m.e0 = m.a - m.e1;
+    return m;
+}
+
+AxisTables build_axis_tables(const TableInput &in, int nabla, int nb, int ntr)
+{
+    AxisTables t;
+    const int L = in.L;
+    t.n_slots = nabla == 2 ? nb + 1 : nb + 2;
+    t.w.assign((size_t)t.n_slots * in.n_labels, 0.0f);
+    t.bc.assign((size_t)t.n_slots * in.n_labels * L * 2, 0.0f);
+    const int row_len = 2 + 4 * L;
+    for (int s = 0; s < t.n_slots; ++s) {
+        double dist;
+        if (nabla == 2) dist = (double)s;
+        else dist = s == 0 ? 0.0 : std::min((double)s - 0.5, (double)nb);
+        for (int lab = 0; lab < in.n_labels; ++lab) {
+            const double *row = in.table + (size_t)lab * row_len;
+            const double kappa = nabla == 1 ? row[0] : row[1];
+            const double *dv = row + 2 + (nabla == 1 ? 0 : L);
+            const double *av = row + 2 + 2 * L + (nabla == 1 ? 0 : L);
+            double w = 1.0 / kappa;
+            for (int nu = 0; nu < L; ++nu) {
+                double d, al;
+                layer_profile(dist, in.h, nb, ntr, dv[nu], av[nu], nu + 1, in.d_target, in.npoly, &d, &al);
+                const MechCoef m = mech_coef(kappa, d, al, in.dt);
+                double c;
+                if (in.scheme == 0) {
+                    c = m.a;
+                } else {
+                    w += m.e0;
+                    c = m.e1 + m.b * m.e0;
+                }
+                const size_t o = (((size_t)s * in.n_labels + lab) * L + nu) * 2;
+                t.bc[o] = (float)m.b;
+                t.bc[o + 1] = (float)c;
+            }
+            t.w[(size_t)s * in.n_labels + lab] = (float)w;
+        }
+    }
+    return t;
+}
+
+}  // namespace fw2

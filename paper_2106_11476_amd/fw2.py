@@ -1,0 +1,286 @@
+"""Thin ctypes binding of libfw2 (include/fw2.h).
+
+Argument marshalling only: every step of the solver runs in the HIP library.
+PyTorch provides device memory (the workspace, source tables, traces) and the
+stream.  The binding fails loudly if the library has not been built.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfw2.so")
+
+FW2_OK = 0
+STATUS = {0: "FW2_OK", 1: "FW2_E_INVALID", 2: "FW2_E_NOMEM", 3: "FW2_E_HIP", 4: "FW2_E_STATE",
+          5: "FW2_E_UNSTABLE", 6: "FW2_E_UNSUPPORTED"}
+FIELD_P, FIELD_V, FIELD_PSI1, FIELD_PSI2, FIELD_ALL = 1, 2, 4, 8, 15
+HOST, DEVICE = 0, 1
+RELAX_PRINTED, RELAX_CENTRED = 0, 1
+
+EXPORTS = ["fw2_workspace_bytes", "fw2_create_domain", "fw2_add_source", "fw2_add_receivers",
+           "fw2_step", "fw2_read_fields", "fw2_write_fields", "fw2_current_step",
+           "fw2_set_current_step", "fw2_set_graph_chunk", "fw2_enable_kernel_timing",
+           "fw2_get_kernel_timing", "fw2_check_finite", "fw2_last_error", "fw2_destroy_domain"]
+
+
+class Fw2Error(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (STATUS.get(status, status), msg))
+        self.status = status
+
+
+class DomainDesc(ctypes.Structure):
+    _fields_ = [
+        ("ndim", ctypes.c_int32), ("n_relax", ctypes.c_int32), ("n", ctypes.c_int64 * 3),
+        ("h", ctypes.c_double), ("dt", ctypes.c_double),
+        ("bound_cells", ctypes.c_int32 * 3), ("trans_cells", ctypes.c_int32 * 3),
+        ("pml_Rc", ctypes.c_double), ("pml_npoly", ctypes.c_int32), ("pml_cp", ctypes.c_double),
+        ("fd_r", ctypes.c_double), ("relax_scheme", ctypes.c_int32),
+        ("c", ctypes.c_void_p), ("rho", ctypes.c_void_p), ("beta", ctypes.c_void_p),
+        ("label", ctypes.c_void_p), ("n_labels", ctypes.c_int32), ("relax_table", ctypes.c_void_p),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """Load libfw2.so; raise if it is missing (there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libfw2.so is not built (run __graft_entry__.build()); there is no CPU fallback")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, u32, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64
+        sig = {
+            "fw2_workspace_bytes": [ctypes.POINTER(DomainDesc), ctypes.POINTER(u64)],
+            "fw2_create_domain": [ctypes.POINTER(DomainDesc), vp, u64, ctypes.POINTER(vp)],
+            "fw2_add_source": [vp, i32, vp, vp, vp, i32, i32, vp],
+            "fw2_add_receivers": [vp, i32, vp, vp, i64],
+            "fw2_step": [vp, i32],
+            "fw2_read_fields": [vp, u32, vp, i32],
+            "fw2_write_fields": [vp, u32, vp, i32],
+            "fw2_set_current_step": [vp, i64],
+            "fw2_set_graph_chunk": [vp, i32],
+            "fw2_enable_kernel_timing": [vp, i32],
+            "fw2_get_kernel_timing": [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)],
+            "fw2_check_finite": [vp, ctypes.c_float],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = ctypes.c_int
+        L.fw2_current_step.argtypes = [vp]
+        L.fw2_current_step.restype = i64
+        L.fw2_last_error.argtypes = []
+        L.fw2_last_error.restype = ctypes.c_char_p
+        L.fw2_destroy_domain.argtypes = [vp]
+        L.fw2_destroy_domain.restype = None
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != FW2_OK:
+        raise Fw2Error(status, lib().fw2_last_error().decode())
+
+
+def make_desc(prob, stream=None):
+    """Fill a DomainDesc from a problem description (workloads.Problem-like).
+
+    Returns (desc, keepalive) -- the numpy buffers must outlive the call that
+    consumes desc."""
+    nd = len(prob.shape)
+    keep = []
+
+    def host(arr, dtype):
+        a = np.ascontiguousarray(np.asarray(arr), dtype=dtype)
+        keep.append(a)
+        return a.ctypes.data
+
+    d = DomainDesc()
+    d.ndim = nd
+    d.n_relax = int(prob.n_relax)
+    n3 = list(prob.shape) + [1] * (3 - nd)
+    for a in range(3):
+        d.n[a] = int(n3[a])
+        d.bound_cells[a] = int(prob.bound_cells[a]) if a < nd else 0
+        d.trans_cells[a] = int(prob.trans_cells[a]) if a < nd else 0
+    d.h, d.dt = float(prob.h), float(prob.dt)
+    d.pml_Rc, d.pml_npoly, d.pml_cp = float(prob.pml_Rc), int(prob.pml_npoly), float(prob.pml_cp or 0.0)
+    d.fd_r = float(prob.fd_r or 0.0)
+    d.relax_scheme = int(getattr(prob, "relax_scheme", RELAX_CENTRED))
+    d.c = host(prob.c, np.float32)
+    d.rho = host(prob.rho, np.float32)
+    d.beta = host(prob.beta, np.float32)
+    table = np.asarray(prob.relax_table, dtype=np.float64)
+    d.n_labels = int(table.shape[0])
+    d.relax_table = host(table, np.float64)
+    d.label = host(prob.label, np.uint8) if (prob.label is not None and d.n_labels > 1) else None
+    d.stream = stream.value if isinstance(stream, ctypes.c_void_p) else stream
+    return d, keep
+
+
+def workspace_bytes(prob):
+    d, keep = make_desc(prob)
+    out = ctypes.c_uint64(0)
+    _check(lib().fw2_workspace_bytes(ctypes.byref(d), ctypes.byref(out)))
+    return int(out.value)
+
+
+class Domain:
+    """One simulation domain resident on the GPU (fw2_create_domain).
+
+    The workspace is a torch uint8 tensor; sources, receivers and traces are
+    torch device tensors held by this object for as long as the library may
+    read them."""
+
+    def __init__(self, prob, device="cuda", stream=None):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.shape = tuple(int(s) for s in prob.shape)
+        self.ndim = len(self.shape)
+        self.L = int(prob.n_relax)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        d, keep = make_desc(prob, ctypes.c_void_p(stream.cuda_stream))
+        nbytes = ctypes.c_uint64(0)
+        _check(lib().fw2_workspace_bytes(ctypes.byref(d), ctypes.byref(nbytes)))
+        self.workspace_bytes = int(nbytes.value)
+        with torch.cuda.device(self.device):
+            self.workspace = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self.device)
+        torch.cuda.synchronize(self.device)
+        h = ctypes.c_void_p()
+        _check(lib().fw2_create_domain(ctypes.byref(d), ctypes.c_void_p(self.workspace.data_ptr()),
+                                       self.workspace_bytes, ctypes.byref(h)))
+        self._h = h
+        del keep
+        self._src = None
+        self._rcv = None
+        self.trace = None
+
+    # -- C entry points -------------------------------------------------
+    def add_source(self, flat_idx, sig_id, weight, signals):
+        t = self.torch
+        idx = t.as_tensor(np.asarray(flat_idx, np.int64), device=self.device).contiguous()
+        sig = t.as_tensor(np.asarray(sig_id, np.int32), device=self.device).contiguous()
+        w = t.as_tensor(np.asarray(weight, np.float32), device=self.device).contiguous()
+        s = np.asarray(signals, np.float32)
+        if s.ndim == 1:
+            s = s[None, :]
+        sg = t.as_tensor(np.ascontiguousarray(s), device=self.device).contiguous()
+        t.cuda.synchronize(self.device)
+        _check(lib().fw2_add_source(self._h, int(idx.numel()), ctypes.c_void_p(idx.data_ptr()),
+                                    ctypes.c_void_p(sig.data_ptr()), ctypes.c_void_p(w.data_ptr()),
+                                    int(sg.shape[0]), int(sg.shape[1]), ctypes.c_void_p(sg.data_ptr())))
+        self._src = (idx, sig, w, sg)
+
+    def add_receivers(self, flat_idx, cap_steps):
+        t = self.torch
+        idx = t.as_tensor(np.asarray(flat_idx, np.int64), device=self.device).contiguous()
+        n = int(idx.numel())
+        trace = t.zeros((int(cap_steps), max(n, 1)), dtype=t.float32, device=self.device)
+        t.cuda.synchronize(self.device)
+        _check(lib().fw2_add_receivers(self._h, n, ctypes.c_void_p(idx.data_ptr()),
+                                       ctypes.c_void_p(trace.data_ptr()), int(cap_steps)))
+        self._rcv = idx
+        self.trace = trace[:, :n]
+
+    def step(self, n):
+        _check(lib().fw2_step(self._h, int(n)))
+
+    def current_step(self):
+        return int(lib().fw2_current_step(self._h))
+
+    def set_current_step(self, step):
+        _check(lib().fw2_set_current_step(self._h, int(step)))
+
+    def set_graph_chunk(self, steps):
+        _check(lib().fw2_set_graph_chunk(self._h, int(steps)))
+
+    def enable_kernel_timing(self, enable=True):
+        _check(lib().fw2_enable_kernel_timing(self._h, 1 if enable else 0))
+
+    def get_kernel_timing(self):
+        ms = (ctypes.c_double * 2)()
+        cnt = (ctypes.c_int64 * 2)()
+        _check(lib().fw2_get_kernel_timing(self._h, ms, cnt))
+        return [ms[0], ms[1]], [cnt[0], cnt[1]]
+
+    def check_finite(self, limit=1e12):
+        _check(lib().fw2_check_finite(self._h, float(limit)))
+
+    def _sizes(self, mask):
+        grid = self.shape[::-1]
+        out = []
+        if mask & FIELD_P:
+            out.append(("p", grid))
+        if mask & FIELD_V:
+            out.append(("v", (self.ndim,) + grid))
+        if mask & FIELD_PSI1:
+            out.append(("psi1", (self.ndim, self.L) + grid))
+        if mask & FIELD_PSI2:
+            out.append(("psi2", (self.ndim, self.L) + grid))
+        return out
+
+    def read_fields(self, mask=FIELD_ALL):
+        """Return {name: float32 numpy array} of the selected fields."""
+        parts = self._sizes(mask)
+        total = sum(int(np.prod(s)) for _, s in parts)
+        buf = np.empty(total, np.float32)
+        _check(lib().fw2_read_fields(self._h, mask, ctypes.c_void_p(buf.ctypes.data), HOST))
+        out, o = {}, 0
+        for name, s in parts:
+            k = int(np.prod(s))
+            out[name] = buf[o:o + k].reshape(s)
+            o += k
+        return out
+
+    def read_fields_device(self, mask=FIELD_ALL):
+        """Selected fields packed into one torch device tensor."""
+        total = sum(int(np.prod(s)) for _, s in self._sizes(mask))
+        buf = self.torch.empty(total, dtype=self.torch.float32, device=self.device)
+        _check(lib().fw2_read_fields(self._h, mask, ctypes.c_void_p(buf.data_ptr()), DEVICE))
+        return buf
+
+    def write_fields(self, fields, mask=None):
+        """fields: dict name -> array (names as read_fields returns)."""
+        if mask is None:
+            mask = sum(b for n, b in (("p", FIELD_P), ("v", FIELD_V), ("psi1", FIELD_PSI1),
+                                      ("psi2", FIELD_PSI2)) if n in fields)
+        parts = self._sizes(mask)
+        buf = np.concatenate([np.asarray(fields[n], np.float32).reshape(-1) for n, _ in parts])
+        _check(lib().fw2_write_fields(self._h, mask, ctypes.c_void_p(buf.ctypes.data), HOST))
+
+    def destroy_domain(self):
+        if getattr(self, "_h", None):
+            lib().fw2_destroy_domain(self._h)
+            self._h = None
+
+    close = destroy_domain
+
+    def __del__(self):
+        try:
+            self.destroy_domain()
+        except Exception:
+            pass
+
+
+def create_domain(prob, device="cuda", stream=None):
+    """fw2_create_domain for a problem description; returns a Domain."""
+    return Domain(prob, device=device, stream=stream)
+
+
+def from_problem(prob, device="cuda", stream=None, cap_steps=None):
+    """Domain with the problem's sources and receivers attached."""
+    dom = Domain(prob, device=device, stream=stream)
+    if len(prob.src_idx):
+        dom.add_source(prob.src_idx, prob.src_sig, prob.src_w, prob.signals)
+    if len(prob.rcv_idx):
+        dom.add_receivers(prob.rcv_idx, cap_steps if cap_steps is not None else max(int(prob.n_steps), 1))
+    return dom

@@ -1,0 +1,272 @@
+"""GPU parity: the HIP library (through the C ABI) against the FP64 oracle on
+the same seeded inputs.  Bar: relative L2 <= 1e-4 and max-abs <= 1e-3 of the
+peak pressure for p and the traces (and rel L2 <= 1e-4 for v and the memory
+variables).  Every test prints its case before touching the GPU."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import solver
+
+pytestmark = pytest.mark.gpu
+
+REL_L2 = 1e-4
+MAX_ABS = 1e-3
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _say(*a):
+    print("[gpu-case]", *a, flush=True)
+
+
+def gpu_run(prob, n_steps, state=None, chunks=None, graph_chunk=None, cap=None):
+    torch = _torch()
+    from paper_2106_11476_amd import fw2
+    dom = fw2.from_problem(prob, device="cuda:0", cap_steps=cap if cap else max(n_steps, 1))
+    if graph_chunk is not None:
+        dom.set_graph_chunk(graph_chunk)
+    if state is not None:
+        dom.write_fields(state)
+    for n in (chunks or [n_steps]):
+        dom.step(n)
+    torch.cuda.synchronize()
+    f = dom.read_fields(fw2.FIELD_ALL)
+    tr = dom.trace.cpu().numpy() if dom.trace is not None else None
+    step = dom.current_step()
+    dom.destroy_domain()
+    return f, tr, step
+
+
+def oracle_run(prob, n_steps, state=None):
+    st = None
+    if state is not None:
+        st = solver.State(prob.ndim, prob.n_relax, prob.c.shape)
+        st.p = state["p"].astype(np.float64)
+        st.v = state["v"].astype(np.float64)
+        st.psi1 = state["psi1"].astype(np.float64)
+        st.psi2 = state["psi2"].astype(np.float64)
+    st, tr = solver.run(prob, n_steps, st)
+    return st, tr
+
+
+def rel_l2(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / nb if nb > 0 else np.linalg.norm(a)
+
+
+def compare(f, tr, ref, rtr, label, check_all=True):
+    peak = np.abs(ref.p).max()
+    if rtr is not None and rtr.size:
+        peak = max(peak, np.abs(rtr).max())
+    e_p = rel_l2(f["p"], ref.p)
+    m_p = np.abs(f["p"] - ref.p).max() / peak
+    _say(label, "p rel %.2e max/peak %.2e" % (e_p, m_p))
+    assert e_p <= REL_L2, (label, e_p)
+    assert m_p <= MAX_ABS, (label, m_p)
+    if rtr is not None and rtr.size:
+        e_t = rel_l2(tr[:rtr.shape[0]], rtr)
+        m_t = np.abs(tr[:rtr.shape[0]] - rtr).max() / peak
+        _say(label, "trace rel %.2e max/peak %.2e" % (e_t, m_t))
+        assert e_t <= REL_L2 and m_t <= MAX_ABS, (label, e_t, m_t)
+    if check_all:
+        for name in ("v", "psi1", "psi2"):
+            e = rel_l2(f[name], getattr(ref, name))
+            assert e <= REL_L2, (label, name, e)
+
+
+def _state(prob, seed):
+    p, v, psi1, psi2 = W.random_state(prob.ndim, prob.n_relax, prob.shape, seed)
+    # samples past the grid along their axis are held at zero
+    for a in range(prob.ndim):
+        sl = [slice(None)] * prob.ndim
+        sl[prob.ndim - 1 - a] = -1
+        v[a][tuple(sl)] = 0
+        for nu in range(prob.n_relax):
+            psi1[a, nu][tuple(sl)] = 0
+    return {"p": p, "v": v, "psi1": psi1, "psi2": psi2}
+
+
+# --------------------------------------------------------------- workloads ---
+
+def test_plain_2d_full_workload():
+    """384^2 interior + 4 lambda layer, water, L = 2 fitted to 0.5 dB/MHz^1.1/cm,
+    12 ppw at 2 MHz, CFL 0.4, line source, 1000 steps, 64 receivers."""
+    prob = W.plain_2d()
+    _say("plain_2d 480x480 L=2 1000 steps")
+    f, tr, step = gpu_run(prob, prob.n_steps)
+    ref, rtr = oracle_run(prob, prob.n_steps)
+    assert step == prob.n_steps
+    compare(f, tr, ref, rtr, "plain_2d")
+
+
+def test_heterogeneous_2d_small_grid():
+    """The layered abdominal-wall recipe (L = 4, labels, scatterers, array
+    source) on a 320 x 224 grid, 1500 steps."""
+    prob = W.abdominal_2d(nx=320, ny=224, n_steps=1500, n_scatter=2000)
+    _say("abdominal_2d 320x224 L=4 1500 steps")
+    f, tr, _ = gpu_run(prob, prob.n_steps)
+    ref, rtr = oracle_run(prob, prob.n_steps)
+    compare(f, tr, ref, rtr, "abdominal_2d_small")
+
+
+def test_heterogeneous_2d_full_size_random_state():
+    """Full 4096 x 2048 grid of the heterogeneous workload in the benchmark's
+    launch configuration (graph chunks): a seeded random state advanced a few
+    steps matches the oracle everywhere."""
+    prob = W.abdominal_2d()
+    st = _state(prob, 21)
+    _say("abdominal_2d 4096x2048 L=4 random state, 6 steps (graph chunk 2)")
+    f, tr, _ = gpu_run(prob, 6, state=st, graph_chunk=2)
+    ref, rtr = oracle_run(prob, 6, state=st)
+    compare(f, tr, ref, rtr, "abdominal_2d_full")
+
+
+# -------------------------------------------------------- random states ---
+
+@pytest.mark.parametrize("shape,L,scheme,labels", [
+    ((67, 45), 1, 1, 1), ((67, 45), 2, 0, 3), ((131, 70), 3, 1, 4), ((64, 64), 4, 1, 2),
+    ((19, 23, 17), 2, 1, 2), ((33, 20, 21), 4, 0, 3), ((9, 7, 6), 1, 1, 1),
+])
+def test_random_state_parity(shape, L, scheme, labels):
+    prob = W.random_medium(shape, L, labels, seed=sum(shape) + L, nb=min(6, min(shape) // 2 - 1), ntr=2)
+    prob.relax_scheme = scheme
+    rng = np.random.default_rng(3)
+    n = prob.npts
+    prob.src_idx = np.unique(rng.integers(0, n, 7)).astype(np.int64)
+    prob.src_sig = rng.integers(0, 2, prob.src_idx.size).astype(np.int32)
+    prob.src_w = rng.uniform(-1, 1, prob.src_idx.size).astype(np.float32)
+    prob.signals = (1e4 * rng.standard_normal((2, 30))).astype(np.float32)
+    prob.rcv_idx = rng.integers(0, n, 9).astype(np.int64)
+    st = _state(prob, 5)
+    _say("random state", shape, "L", L, "scheme", scheme, "labels", labels)
+    f, tr, _ = gpu_run(prob, 25, state=st)
+    ref, rtr = oracle_run(prob, 25, state=st)
+    compare(f, tr, ref, rtr, "random %s" % (shape,))
+
+
+def test_3d_point_source():
+    prob = W.homogeneous((40, 36, 34), L=2, nb=(8, 8, 8), ntr=(6, 6, 6))
+    prob.src_idx = prob.flat(np.array([20]), np.array([18]), np.array([17]))
+    prob.src_sig = np.zeros(1, np.int32)
+    prob.src_w = np.ones(1, np.float32)
+    prob.signals = W.gaussian_pulse(300, prob.dt, 2e6, 3, 1e5)[None]
+    prob.rcv_idx = prob.flat(np.array([5, 20, 33]), np.array([18, 30, 4]), np.array([17, 10, 28]))
+    _say("3d 40x36x34 point source 300 steps")
+    f, tr, _ = gpu_run(prob, 300)
+    ref, rtr = oracle_run(prob, 300)
+    compare(f, tr, ref, rtr, "3d point")
+
+
+# ---------------------------------------------------------- edge cases ---
+
+def test_degenerate_grids():
+    for shape in [(1, 1), (1, 7), (5, 1), (2, 3, 1), (1, 1, 1)]:
+        prob = W.homogeneous(shape, L=1, nb=(0,) * len(shape), ntr=(0,) * len(shape))
+        st = _state(prob, 1)
+        _say("degenerate", shape)
+        f, tr, _ = gpu_run(prob, 4, state=st)
+        ref, _ = oracle_run(prob, 4, state=st)
+        compare(f, None, ref, None, "degenerate %s" % (shape,))
+
+
+def test_split_steps_graph_and_direct_are_bitwise_equal():
+    prob = W.plain_2d(interior=120, n_steps=200, n_rcv=8)
+    _say("bitwise split/graph 216x216")
+    a, ta, sa = gpu_run(prob, 200, graph_chunk=0)
+    b, tb, sb = gpu_run(prob, 200, chunks=[0, 37, 100, 63], graph_chunk=16)
+    c, tc, _ = gpu_run(prob, 200, graph_chunk=200)
+    assert sa == sb == 200
+    for k in a:
+        assert np.array_equal(a[k], b[k]) and np.array_equal(a[k], c[k]), k
+    assert np.array_equal(ta, tb) and np.array_equal(ta, tc)
+
+
+def test_checkpoint_resume_is_bitwise():
+    torch = _torch()
+    from paper_2106_11476_amd import fw2
+    prob = W.abdominal_2d(nx=256, ny=160, n_steps=300, n_scatter=500)
+    _say("checkpoint/resume 256x160")
+    full, tf, _ = gpu_run(prob, 300)
+    dom = fw2.from_problem(prob, device="cuda:0", cap_steps=300)
+    dom.step(140)
+    ck = dom.read_fields(fw2.FIELD_ALL)
+    step = dom.current_step()
+    dom.destroy_domain()
+    dom2 = fw2.from_problem(prob, device="cuda:0", cap_steps=300)
+    dom2.write_fields(ck)
+    dom2.set_current_step(step)
+    dom2.step(160)
+    torch.cuda.synchronize()
+    res = dom2.read_fields(fw2.FIELD_ALL)
+    t2 = dom2.trace.cpu().numpy()
+    dom2.destroy_domain()
+    for k in full:
+        assert np.array_equal(full[k], res[k]), k
+    assert np.array_equal(tf[140:], t2[140:])
+
+
+def test_zero_steps_and_write_read_roundtrip():
+    torch = _torch()
+    from paper_2106_11476_amd import fw2
+    prob = W.random_medium((37, 29, 11), 3, 2, seed=4, nb=3, ntr=2)
+    st = _state(prob, 8)
+    _say("roundtrip 37x29x11")
+    dom = fw2.from_problem(prob, device="cuda:0")
+    dom.write_fields(st)
+    dom.step(0)
+    back = dom.read_fields(fw2.FIELD_ALL)
+    dev = dom.read_fields_device(fw2.FIELD_P | fw2.FIELD_PSI2).cpu().numpy()
+    dom.destroy_domain()
+    for k in st:
+        assert np.array_equal(back[k], st[k]), k
+    assert np.array_equal(dev, np.concatenate([st["p"].ravel(), st["psi2"].ravel()]))
+
+
+def test_invalid_calls_and_watchdog():
+    torch = _torch()
+    from paper_2106_11476_amd import fw2
+    prob = W.plain_2d(interior=64, n_steps=10, n_rcv=4)
+    _say("invalid calls 160x160")
+    dom = fw2.from_problem(prob, device="cuda:0")
+    with pytest.raises(fw2.Fw2Error):
+        dom.add_source([5, 5], [0, 0], [1, 1], np.ones((1, 3)))          # duplicate index
+    with pytest.raises(fw2.Fw2Error):
+        dom.add_source([prob.npts], [0], [1], np.ones((1, 3)))          # out of range
+    with pytest.raises(fw2.Fw2Error):
+        dom.add_receivers([-1], 5)
+    with pytest.raises(fw2.Fw2Error):
+        dom.step(-1)
+    dom.step(10)
+    dom.check_finite(1e12)
+    f = dom.read_fields(fw2.FIELD_P)
+    f["p"][3, 4] = np.nan
+    dom.write_fields(f)
+    with pytest.raises(fw2.Fw2Error) as e:
+        dom.check_finite(1e12)
+    assert e.value.status == 5
+    dom.destroy_domain()
+    # a time step above the stability bound is refused at creation
+    bad = W.plain_2d(interior=64, n_steps=10)
+    bad.dt *= 1.8
+    with pytest.raises(fw2.Fw2Error):
+        fw2.from_problem(bad, device="cuda:0")
+
+
+def test_kernel_timing_counts_launches():
+    torch = _torch()
+    from paper_2106_11476_amd import fw2
+    prob = W.plain_2d(interior=64, n_steps=50, n_rcv=4)
+    _say("kernel timing 160x160")
+    dom = fw2.from_problem(prob, device="cuda:0", cap_steps=600)
+    dom.enable_kernel_timing(True)
+    dom.step(300)
+    ms, cnt = dom.get_kernel_timing()
+    assert cnt == [300, 300] and ms[0] > 0 and ms[1] > 0
+    dom.enable_kernel_timing(False)
+    dom.destroy_domain()
