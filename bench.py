@@ -1,0 +1,269 @@
+#!/usr/bin/env python
+"""Benchmark of the Fullwave 2 time stepper on one MI355X.
+
+A step is one time step of the whole hot path: pressure kernel, sources,
+receivers, velocity kernel, over the heterogeneous abdominal-wall-like 2D
+workload (4096 x 2048 points including the 4-wavelength boundary, L = 4
+relaxation mechanisms, 9 tissue labels, 128-element array, 3 MHz).
+
+Prints one JSON line: Gpoint-updates/s over the timed steps, the roofline of
+the dominant kernel (HIP-event durations on the domain's stream, algorithmic
+bytes per launch) and the FP64 CPU oracle timed on a bounded sample.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload abdominal_2d|plain_2d]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, 8 TB/s
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2106_11476_amd", "csrc", "kernels.hip")
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def kernel_source_sha():
+    import hashlib
+    with open(KERNEL_SOURCE, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch from the committed counter summary of this kernel
+    and workload, or None when there is none or the kernel source changed
+    since the counters were taken."""
+    path = os.path.join(PROFILES, "traffic_%s_%s.txt" % (kernel, workload))
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and not line.startswith(" "):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256_16") != kernel_source_sha():
+        return None
+    try:
+        return int(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def kernel_bytes(ndim, L, labels):
+    """Algorithmic bytes per point of each kernel (every array it must touch,
+    read once and written once; the label byte only when tissues vary).
+    pressure: reads v (ndim), p, psi2 (ndim L), kappa0, kappa0(1-2 beta);
+              writes p, psi2.
+    velocity: reads p, v (ndim), psi1 (ndim L), rho, kappa0; writes v, psi1.
+    step:     each state array read and written once, three medium arrays
+              read once, the label once."""
+    lab = 1 if labels else 0
+    p_b = 4 * (ndim + 1 + ndim * L + 2) + lab + 4 * (1 + ndim * L)
+    v_b = 4 * (1 + ndim + ndim * L + 2) + lab + 4 * (ndim + ndim * L)
+    state = 1 + ndim + 2 * ndim * L
+    step_b = 8 * state + 12 + lab
+    return p_b, v_b, step_b
+
+
+def make_workload(name):
+    import workloads as W
+    if name == "abdominal_2d":
+        return W.abdominal_2d()
+    if name == "plain_2d":
+        return W.plain_2d()
+    raise SystemExit("unknown workload %s" % name)
+
+
+def cpu_baseline(prob, target_s=15.0):
+    """The FP64 oracle, as is, on the same workload: a bounded number of
+    steps on the full grid from the zero state (setup not timed)."""
+    from oracle import solver
+    maps = solver.coefficient_maps(prob)
+    st = solver.State(maps.ndim, maps.L, maps.grid)
+    t0 = time.perf_counter()
+    solver.run(prob, 2, st, maps, record=False)
+    per = (time.perf_counter() - t0) / 2
+    k = int(max(2, min(400, target_s / max(per, 1e-6))))
+    t0 = time.perf_counter()
+    solver.run(prob, k, st, maps, record=False)
+    el = time.perf_counter() - t0
+    return {"value": prob.npts * k / el / 1e9, "unit": "Gpoint-updates/s", "cores": solver.threads(),
+            "kind": "oracle",
+            "sample": "%d steps of the full %s grid (FP64 C stepper, OpenMP), %.1f s" % (k, prob.name, el)}
+
+
+def probe_copy(torch, dev, mib, reps=10):
+    """Plain device-to-device copy of `mib` MiB (one torch copy kernel per rep)."""
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize(dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize(dev)
+    ms = e0.elapsed_time(e1) / reps
+    moved = 2 * n * 4
+    del src, dst
+    return {"bytes_per_copy": moved, "ms": round(ms, 4), "GBps": round(moved / ms / 1e6, 1), "reps": reps}
+
+
+def _db_rows(db, sql):
+    import sqlite3
+    con = sqlite3.connect(db)
+    try:
+        return list(con.execute(sql))
+    finally:
+        con.close()
+
+
+def summarize_profiles(stats_db, fetch_db, write_db, workload, copy_bytes, commands):
+    """Write profiles/*.txt from rocprofv3 results (kernel-trace stats and the
+    FETCH_SIZE / WRITE_SIZE passes).  Counter values are KiB per dispatch;
+    each is scaled by what it reads for the plain copy that reads and writes
+    copy_bytes."""
+    import glob
+    stats = _db_rows(stats_db, "select name, total_calls, total_duration, average from top_kernels")
+    fetch = _db_rows(fetch_db, "select name, avg(counter_value), max(counter_value), count(*) from pmc_events group by name")
+    write = _db_rows(write_db, "select name, avg(counter_value), max(counter_value), count(*) from pmc_events group by name")
+    fmax = {r[0]: r for r in fetch}
+    wmax = {r[0]: r for r in write}
+    copy_name = "__amd_rocclr_copyBuffer"
+    f_scale = copy_bytes / 1024.0 / fmax[copy_name][2]
+    w_scale = copy_bytes / 1024.0 / wmax[copy_name][2]
+    sha = kernel_source_sha()
+    os.makedirs(PROFILES, exist_ok=True)
+    lines = ["rocprofv3 kernel statistics, workload %s" % workload, "commands:"]
+    lines += ["  " + c for c in commands]
+    lines.append("kernel_source_sha256_16: %s" % sha)
+    lines.append("%-70s %8s %12s %10s" % ("kernel", "calls", "total_us", "avg_us"))
+    for name, calls, tot, avg in stats:
+        lines.append("%-70s %8d %12.1f %10.3f" % (name[:70], calls, tot, avg))
+    with open(os.path.join(PROFILES, "kernel_stats_%s.txt" % workload), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    import workloads as W
+    prob = make_workload(workload) if workload in ("abdominal_2d", "plain_2d") else None
+    labels = prob.label is not None and np.asarray(prob.relax_table).shape[0] > 1
+    p_b, v_b, _ = kernel_bytes(prob.ndim, prob.n_relax, labels)
+    for short, key, alg in (("pressure_kernel", "pressure_", p_b), ("velocity_kernel", "velocity_", v_b)):
+        names = [n for n in fmax if key in n]
+        if not names:
+            continue
+        n = names[0]
+        fk, wk = fmax[n][1], wmax[n][1]
+        hbm = int(round((fk * f_scale + wk * w_scale) * 1024))
+        algb = alg * prob.npts
+        avg_us = [r[3] for r in stats if key in r[0]]
+        txt = ["HBM traffic of %s on workload %s" % (n, workload), "commands:"]
+        txt += ["  " + c for c in commands]
+        txt += ["kernel_source_sha256_16: %s" % sha,
+                "dispatches_counted: %d" % fmax[n][3],
+                "fetch_kib_per_dispatch_raw: %.1f" % fk,
+                "write_kib_per_dispatch_raw: %.1f" % wk,
+                "copy_probe_bytes: %d" % copy_bytes,
+                "copy_fetch_kib_raw: %.1f" % fmax[copy_name][2],
+                "copy_write_kib_raw: %.1f" % wmax[copy_name][2],
+                "fetch_scale: %.4f" % f_scale,
+                "write_scale: %.4f" % w_scale,
+                "hbm_bytes_per_launch: %d" % hbm,
+                "algorithmic_bytes_per_launch: %d" % algb,
+                "traffic_over_algorithmic: %.4f" % (hbm / algb),
+                "avg_duration_us_kernel_trace: %s" % (("%.3f" % avg_us[0]) if avg_us else "n/a")]
+        with open(os.path.join(PROFILES, "traffic_%s_%s.txt" % (short, prob.name)), "w") as fh:
+            fh.write("\n".join(txt) + "\n")
+    print("profiles written to", PROFILES)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=12000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--workload", default="abdominal_2d")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="first time a plain device copy of this size (bandwidth reference, "
+                         "and the known-size kernel for scaling HBM counters)")
+    ap.add_argument("--summarize", nargs=3, metavar=("STATS_DB", "FETCH_DB", "WRITE_DB"),
+                    help="write profiles/*.txt from rocprofv3 result databases and exit")
+    ap.add_argument("--copy-read-bytes", type=int, default=256 * (1 << 20),
+                    help="bytes the probe copy reads (and writes) per dispatch")
+    ap.add_argument("--commands", nargs="*", default=[])
+    args = ap.parse_args()
+    if args.summarize:
+        summarize_profiles(*args.summarize, workload=args.workload, copy_bytes=args.copy_read_bytes,
+                           commands=args.commands)
+        return
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2106_11476_amd import fw2
+
+    dev = torch.device("cuda:0")
+    copy_probe = None
+    if args.copy_probe_mib > 0:
+        copy_probe = probe_copy(torch, dev, args.copy_probe_mib)
+    prob = make_workload(args.workload)
+    K, Wm = int(args.steps), int(args.warmup)
+    stream = torch.cuda.Stream(device=dev)
+    dom = fw2.from_problem(prob, device=dev, stream=stream, cap_steps=K + Wm)
+    dom.step(Wm)
+    torch.cuda.synchronize(dev)
+
+    dom.enable_kernel_timing(True)
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
+    dom.step(K)
+    torch.cuda.synchronize(dev)
+    el = time.perf_counter() - t0
+    ms, cnt = dom.get_kernel_timing()
+    dom.enable_kernel_timing(False)
+    dom.check_finite(1e9)
+
+    npts = prob.npts
+    gpts = npts * K / el / 1e9
+    labels = prob.label is not None and np.asarray(prob.relax_table).shape[0] > 1
+    p_b, v_b, step_b = kernel_bytes(prob.ndim, prob.n_relax, labels)
+    avg = [ms[0] / max(cnt[0], 1), ms[1] / max(cnt[1], 1)]     # ms per launch
+    dom_k = 0 if avg[0] >= avg[1] else 1
+    kb = (p_b, v_b)[dom_k] * npts
+    achieved = kb / (avg[dom_k] * 1e-3) / 1e9
+    roof = {"bound": "hbm", "kernel": ("pressure_kernel", "velocity_kernel")[dom_k],
+            "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic(("pressure_kernel", "velocity_kernel")[dom_k], prob.name),
+            "alg_bytes_per_point": (p_b, v_b)[dom_k], "launch_ms": round(avg[dom_k], 5),
+            "other_kernel_ms": round(avg[1 - dom_k], 5),
+            "step_alg_bytes_per_point": step_b,
+            "step_frac": round(gpts * step_b / HBM_PEAK_GBS, 4)}
+    out = {"metric": "Gpoint-updates/s", "value": round(gpts, 3), "unit": "Gpoint-updates/s",
+           "n_gpus": 1, "steps": K, "warmup": Wm, "ms_per_step": round(el / K * 1e3, 5),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": prob.name, "grid": list(prob.shape), "points": npts,
+                      "relax_mechanisms": prob.n_relax,
+                      "labels": int(np.asarray(prob.relax_table).shape[0]),
+                      "relax_scheme": "centred" if prob.relax_scheme == 1 else "printed",
+                      "parallelism": "single GPU"},
+           "roofline": roof}
+    if copy_probe is not None:
+        out["copy_probe"] = copy_probe
+    dom.destroy_domain()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(prob)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

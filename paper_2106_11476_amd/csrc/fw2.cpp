@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -146,6 +147,7 @@ struct fw2_domain {
     long long *counter = nullptr;
     int *flag = nullptr;
     fw2::StepArgs args;
+    fw2::KernelConfig kc;
     fw2::SparseArgs src, rcv;
     hipStream_t stream = nullptr;
     hipStream_t capture = nullptr;
@@ -174,12 +176,12 @@ fw2_status enqueue_step(fw2_domain *d, TimingSlot *ts)
 {
     const int L = d->desc.n_relax, sch = d->desc.relax_scheme;
     if (ts) FW2_HIP(hipEventRecord(ts->ev[0], d->stream));
-    FW2_HIP(fw2::launch_pressure(d->args, L, sch, d->stream));
+    FW2_HIP(fw2::launch_pressure(d->args, L, sch, d->kc, d->stream));
     if (ts) FW2_HIP(hipEventRecord(ts->ev[1], d->stream));
     FW2_HIP(fw2::launch_sources(d->src, d->stream));
     FW2_HIP(fw2::launch_receivers(d->rcv, d->stream));
     if (ts) FW2_HIP(hipEventRecord(ts->ev[2], d->stream));
-    FW2_HIP(fw2::launch_velocity(d->args, L, sch, d->stream));
+    FW2_HIP(fw2::launch_velocity(d->args, L, sch, d->kc, d->stream));
     if (ts) FW2_HIP(hipEventRecord(ts->ev[3], d->stream));
     return FW2_OK;
 }
@@ -187,10 +189,10 @@ fw2_status enqueue_step(fw2_domain *d, TimingSlot *ts)
 fw2_status enqueue_step_on(fw2_domain *d, hipStream_t s)
 {
     const int L = d->desc.n_relax, sch = d->desc.relax_scheme;
-    FW2_HIP(fw2::launch_pressure(d->args, L, sch, s));
+    FW2_HIP(fw2::launch_pressure(d->args, L, sch, d->kc, s));
     FW2_HIP(fw2::launch_sources(d->src, s));
     FW2_HIP(fw2::launch_receivers(d->rcv, s));
-    FW2_HIP(fw2::launch_velocity(d->args, L, sch, s));
+    FW2_HIP(fw2::launch_velocity(d->args, L, sch, d->kc, s));
     return FW2_OK;
 }
 
@@ -442,6 +444,14 @@ fw2_status fw2_create_domain(const fw2_domain_desc *desc, void *dev_workspace, u
         a.nb[ax] = 0;
         a.bc1[ax] = a.bc2[ax] = nullptr;
         a.w1[ax] = a.w2[ax] = nullptr;
+    }
+
+    d->kc = fw2::KernelConfig{nd == 2 ? 1 : 0, 64, 8};
+    if (const char *ev = std::getenv("FW2_KERNEL_CONFIG")) {      // "variant,bx,rows" (tuning runs)
+        int v = 0, bx = 0, ry = 0;
+        if (std::sscanf(ev, "%d,%d,%d", &v, &bx, &ry) == 3 && (v == 0 || (nd == 2 && v == 1)) &&
+            (bx == 64 || bx == 128 || bx == 256) && ry >= 1 && ry <= 1024)
+            d->kc = fw2::KernelConfig{v, bx, ry};
     }
 
     std::memset(&d->src, 0, sizeof(d->src));

@@ -60,9 +60,19 @@ struct SparseArgs {
     long long cap;           // receivers: trace rows
 };
 
+// Kernel variant and tile shape.  variant 0: one thread per point over a
+// (64 x 8) tile, every stencil tap a cached global load (any ndim).
+// variant 1 (2D): row sweeps of `bx` columns x `rows` rows with a register
+// window along y and LDS rings along x.
+struct KernelConfig {
+    int variant;
+    int bx;
+    int rows;
+};
+
 // Launchers (kernels.hip).  All enqueue on `stream` and return the launch error.
-hipError_t launch_pressure(const StepArgs &a, int L, int scheme, hipStream_t stream);
-hipError_t launch_velocity(const StepArgs &a, int L, int scheme, hipStream_t stream);
+hipError_t launch_pressure(const StepArgs &a, int L, int scheme, const KernelConfig &kc, hipStream_t stream);
+hipError_t launch_velocity(const StepArgs &a, int L, int scheme, const KernelConfig &kc, hipStream_t stream);
 hipError_t launch_sources(const SparseArgs &s, hipStream_t stream);
 hipError_t launch_receivers(const SparseArgs &s, hipStream_t stream);   // also advances the counter
 hipError_t launch_fill(float *dst, int64_t n, float value, hipStream_t stream);

@@ -282,3 +282,20 @@ def test_kernel_timing_counts_launches():
     assert cnt == [300, 300] and ms[0] > 0 and ms[1] > 0
     dom.enable_kernel_timing(False)
     dom.destroy_domain()
+
+
+# ------------------------------------------------- kernel variants / tiles ---
+
+@pytest.mark.parametrize("config", ["0,64,16", "1,64,16", "1,128,7", "1,256,33", "1,64,1"])
+@pytest.mark.parametrize("shape,L,scheme", [((70, 45), 2, 1), ((257, 131), 4, 1), ((131, 90), 3, 0)])
+def test_kernel_variants_match_oracle(monkeypatch, config, shape, L, scheme):
+    """Every kernel variant and tile shape (including tiles that overhang
+    the grid and one-row tiles) gives oracle results."""
+    monkeypatch.setenv("FW2_KERNEL_CONFIG", config)
+    prob = W.random_medium(shape, L, 3, seed=7, nb=8, ntr=5)
+    prob.relax_scheme = scheme
+    st = _state(prob, 13)
+    _say("variant", config, shape, "L", L, "scheme", scheme)
+    f, tr, _ = gpu_run(prob, 12, state=st)
+    ref, rtr = oracle_run(prob, 12, state=st)
+    compare(f, tr, ref, rtr, "variant %s %s" % (config, shape), prob=prob)
