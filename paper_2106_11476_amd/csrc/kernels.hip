@@ -172,14 +172,71 @@ __device__ __forceinline__ int tile_of_block(int bid, int nblocks)
     return (bid % 8) * (nblocks / 8) + bid / 8;
 }
 
-// Value of a padded array at (x, y) inside the grid, else 0 (no access).
-__device__ __forceinline__ float ld2(const float *__restrict__ f, const Geometry &g, int x, int y)
+// Value of a padded array at (x, y): inside the grid the sample itself, else
+// the halo cell (-1, -1), which is zero in every array (never written), so
+// the load is branch-free.
+__device__ __forceinline__ float ldz(const float *__restrict__ f, const Geometry &g, int x, int y)
 {
-    if (x < 0 || x >= g.n[0] || y < 0 || y >= g.n[1]) return 0.0f;
-    return f[g.origin + (int64_t)y * g.pitch + x];
+    const bool in = (unsigned)x < (unsigned)g.n[0] && (unsigned)y < (unsigned)g.n[1];
+    const int64_t o = in ? g.origin + (int64_t)y * g.pitch + x : g.origin - g.pitch - 1;
+    return f[o];
 }
 
-template <int L, bool CENTRED, int BX>
+// LDS hand-off between the threads of a block.  A one-wavefront block needs
+// no hardware barrier (a wavefront's LDS operations complete in order); the
+// fences keep the compiler from moving LDS accesses across it, and global
+// loads of the next row stay in flight.
+template <int BX>
+__device__ __forceinline__ void lds_sync()
+{
+    if constexpr (BX == 64) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
+
+// Column of halo lane t (t < 8) of a tile starting at x0: x0-4..x0-1 and
+// x0+BX..x0+BX+3; its slot in an LDS row whose column c holds x0 - 4 + c.
+template <int BX>
+__device__ __forceinline__ int halo_x(int t, int x0) { return t < 4 ? x0 - 4 + t : x0 + BX + (t - 4); }
+template <int BX>
+__device__ __forceinline__ int halo_c(int t) { return t < 4 ? t : BX + t; }
+
+template <int L>
+struct PRow {                 // everything the pressure sweep loads for one row
+    float vyn, vxn, hx, hy;   // window row j+3, ring row j+1, halos
+    float p0, k0, q0;
+    int l;
+    float m[2][L];
+};
+
+template <int L, int BX>
+__device__ __forceinline__ void p_load_row(PRow<L> &r, const StepArgs &a, int i, int t, int x0, int j, bool live)
+{
+    const Geometry &g = a.geo;
+    const float *__restrict__ vx = a.v;
+    const float *__restrict__ vy = a.v + g.stride;
+    r.vyn = ldz(vy, g, i, j + 3);
+    r.vxn = ldz(vx, g, i, j + 1);
+    r.hx = t < 8 ? ldz(vx, g, halo_x<BX>(t, x0), j + 1) : 0.0f;
+    r.hy = t < 2 ? ldz(vy, g, t == 0 ? x0 - 1 : x0 + BX, j) : 0.0f;
+    const int64_t idx = g.origin + (int64_t)j * g.pitch + i;
+    if (live) {
+        r.p0 = a.p[idx];
+        r.k0 = a.kap[idx];
+        r.q0 = a.nlq[idx];
+        r.l = a.label ? (int)a.label[idx] : 0;
+#pragma unroll
+        for (int ax = 0; ax < 2; ++ax)
+#pragma unroll
+            for (int nu = 0; nu < L; ++nu) r.m[ax][nu] = a.psi2[(int64_t)(ax * L + nu) * g.stride + idx];
+    }
+}
+
+template <int L, bool CENTRED, int BX, bool PF>
 __global__ void __launch_bounds__(BX) pressure_sweep2d(const StepArgs a, int rows, int nbx, int nblocks)
 {
     const Geometry &g = a.geo;
@@ -188,14 +245,11 @@ __global__ void __launch_bounds__(BX) pressure_sweep2d(const StepArgs a, int row
     const int t = threadIdx.x;
     const int i = x0 + t;
     const int nx = g.n[0], ny = g.n[1];
-    const int64_t P = g.pitch;
+    const bool live = i < nx;
     const float *__restrict__ vx = a.v;
     const float *__restrict__ vy = a.v + g.stride;
     float *__restrict__ pp = a.p;
     float *__restrict__ psi = a.psi2;
-    const float *__restrict__ kap = a.kap;
-    const float *__restrict__ nlq = a.nlq;
-    const uint8_t *__restrict__ lab = a.label;
 
     __shared__ float sx[4][BX + 8];     // v_x rows, column c <-> x0 - 4 + c
     __shared__ float sy[3][BX + 2];     // v_y rows, column c <-> x0 - 1 + c
@@ -204,90 +258,103 @@ __global__ void __launch_bounds__(BX) pressure_sweep2d(const StepArgs a, int row
     float w[8];
     w[0] = 0.0f;
 #pragma unroll
-    for (int k = 1; k < 8; ++k) w[k] = ld2(vy, g, i, y0 - 5 + k);
+    for (int k = 1; k < 8; ++k) w[k] = ldz(vy, g, i, y0 - 5 + k);
 #pragma unroll
     for (int r = -1; r <= 0; ++r) {
-        sx[(y0 + r) & 3][t + 4] = ld2(vx, g, i, y0 + r);
-        if (t < 8) {
-            const int xc = t < 4 ? x0 - 4 + t : x0 + BX + (t - 4);
-            sx[(y0 + r) & 3][t < 4 ? t : BX + t] = ld2(vx, g, xc, y0 + r);
-        }
+        sx[(y0 + r) & 3][t + 4] = ldz(vx, g, i, y0 + r);
+        if (t < 8) sx[(y0 + r) & 3][halo_c<BX>(t)] = ldz(vx, g, halo_x<BX>(t, x0), y0 + r);
     }
-    sy[(y0 + 2) % 3][t + 1] = ld2(vy, g, i, y0 - 1);
-    if (t < 2) sy[(y0 + 2) % 3][t == 0 ? 0 : BX + 1] = ld2(vy, g, t == 0 ? x0 - 1 : x0 + BX, y0 - 1);
+    sy[(y0 + 2) % 3][t + 1] = ldz(vy, g, i, y0 - 1);
+    if (t < 2) sy[(y0 + 2) % 3][t == 0 ? 0 : BX + 1] = ldz(vy, g, t == 0 ? x0 - 1 : x0 + BX, y0 - 1);
 
-    const int sxs = a.nb[0] > 0 ? max(max(a.nb[0] - i, i - (nx - 1 - a.nb[0])), 0) : 0;
+    const int sxs = max(max(a.nb[0] - i, i - (nx - 1 - a.nb[0])), 0);
     const int yend = min(y0 + rows, ny);
+    PRow<L> cur, nxt;
+    if (PF) p_load_row<L, BX>(cur, a, i, t, x0, y0, live);
     for (int j = y0; j < yend; ++j) {
-        const bool live = i < nx;
-        const int64_t idx = g.origin + (int64_t)j * P + i;
-        // loads of this row
-        const float vyn = ld2(vy, g, i, j + 3);
-        const float vxn = ld2(vx, g, i, j + 1);
-        float hx = 0.0f, hy = 0.0f;
-        if (t < 8) hx = ld2(vx, g, t < 4 ? x0 - 4 + t : x0 + BX + (t - 4), j + 1);
-        if (t < 2) hy = ld2(vy, g, t == 0 ? x0 - 1 : x0 + BX, j);
-        float p0 = 0.0f, k0 = 1.0f, q0 = 0.0f;
-        float m[2][L];
-        int l = 0;
+        if (!PF) p_load_row<L, BX>(cur, a, i, t, x0, j, live);        // rows loaded in turn
+        else if (j + 1 < yend) p_load_row<L, BX>(nxt, a, i, t, x0, j + 1, live);   // next row in flight
+#pragma unroll
+        for (int k = 0; k < 7; ++k) w[k] = w[k + 1];
+        w[7] = cur.vyn;
+        sx[(j + 1) & 3][t + 4] = cur.vxn;
+        if (t < 8) sx[(j + 1) & 3][halo_c<BX>(t)] = cur.hx;
+        sy[j % 3][t + 1] = w[4];
+        if (t < 2) sy[j % 3][t == 0 ? 0 : BX + 1] = cur.hy;
+        lds_sync<BX>();
         if (live) {
-            p0 = pp[idx];
-            k0 = kap[idx];
-            q0 = nlq[idx];
-            l = lab ? (int)lab[idx] : 0;
+            const float *r0 = sx[j & 3], *rp = sx[(j + 1) & 3], *rm = sx[(j + 3) & 3];
+            float Dx = a.g[0] * (r0[t + 4] - r0[t + 3]);
+            Dx = fmaf(a.g[1], r0[t + 5] - r0[t + 2], Dx);
+            Dx = fmaf(a.g[2], r0[t + 6] - r0[t + 1], Dx);
+            Dx = fmaf(a.g[3], r0[t + 7] - r0[t], Dx);
+            Dx = fmaf(a.g11, (rp[t + 4] - rp[t + 3]) + (rm[t + 4] - rm[t + 3]), Dx);
+            const float *c0 = sy[j % 3], *cm = sy[(j + 2) % 3];
+            float Dy = a.g[0] * (w[4] - w[3]);
+            Dy = fmaf(a.g[1], w[5] - w[2], Dy);
+            Dy = fmaf(a.g[2], w[6] - w[1], Dy);
+            Dy = fmaf(a.g[3], w[7] - w[0], Dy);
+            Dy = fmaf(a.g11, (c0[t + 2] - cm[t + 2]) + (c0[t] - cm[t]), Dy);
+            const int sys = max(max(a.nb[1] - j, j - (ny - 1 - a.nb[1])), 0);
+            float S = 0.0f;
+#pragma unroll
+            for (int ax = 0; ax < 2; ++ax) {
+                const float D = ax == 0 ? Dx : Dy;
+                const int tt = (ax == 0 ? sxs : sys) * a.n_labels + cur.l;
+                const float2 *__restrict__ bc = a.bc2[ax] + (int64_t)tt * L;
+                float Sa = a.w2[ax][tt] * D;
+#pragma unroll
+                for (int nu = 0; nu < L; ++nu) {
+                    const float2 q = bc[nu];
+                    const float mn = fmaf(q.x, cur.m[ax][nu], q.y * D);
+                    Sa += CENTRED ? cur.m[ax][nu] : mn;
+                    cur.m[ax][nu] = mn;
+                }
+                S += Sa;
+            }
+            const int64_t idx = g.origin + (int64_t)j * g.pitch + i;
+            const float kappa = cur.k0 * (1.0f + cur.q0 * cur.p0);
+            pp[idx] = cur.p0 - a.dt * S / kappa;
 #pragma unroll
             for (int ax = 0; ax < 2; ++ax)
 #pragma unroll
-                for (int nu = 0; nu < L; ++nu) m[ax][nu] = psi[(int64_t)(ax * L + nu) * g.stride + idx];
+                for (int nu = 0; nu < L; ++nu) psi[(int64_t)(ax * L + nu) * g.stride + idx] = cur.m[ax][nu];
         }
-#pragma unroll
-        for (int k = 0; k < 7; ++k) w[k] = w[k + 1];
-        w[7] = vyn;
-        sx[(j + 1) & 3][t + 4] = vxn;
-        if (t < 8) sx[(j + 1) & 3][t < 4 ? t : BX + t] = hx;
-        sy[j % 3][t + 1] = w[4];
-        if (t < 2) sy[j % 3][t == 0 ? 0 : BX + 1] = hy;
-        __syncthreads();
-        if (!live) continue;
-        const float *r0 = sx[j & 3], *rp = sx[(j + 1) & 3], *rm = sx[(j + 3) & 3];
-        float Dx = a.g[0] * (r0[t + 4] - r0[t + 3]);
-        Dx = fmaf(a.g[1], r0[t + 5] - r0[t + 2], Dx);
-        Dx = fmaf(a.g[2], r0[t + 6] - r0[t + 1], Dx);
-        Dx = fmaf(a.g[3], r0[t + 7] - r0[t], Dx);
-        Dx = fmaf(a.g11, (rp[t + 4] - rp[t + 3]) + (rm[t + 4] - rm[t + 3]), Dx);
-        const float *c0 = sy[j % 3], *cm = sy[(j + 2) % 3];
-        float Dy = a.g[0] * (w[4] - w[3]);
-        Dy = fmaf(a.g[1], w[5] - w[2], Dy);
-        Dy = fmaf(a.g[2], w[6] - w[1], Dy);
-        Dy = fmaf(a.g[3], w[7] - w[0], Dy);
-        Dy = fmaf(a.g11, (c0[t + 2] - cm[t + 2]) + (c0[t] - cm[t]), Dy);
-        const int sys = a.nb[1] > 0 ? max(max(a.nb[1] - j, j - (ny - 1 - a.nb[1])), 0) : 0;
-        float S = 0.0f;
-#pragma unroll
-        for (int ax = 0; ax < 2; ++ax) {
-            const float D = ax == 0 ? Dx : Dy;
-            const int tt = (ax == 0 ? sxs : sys) * a.n_labels + l;
-            const float2 *__restrict__ bc = a.bc2[ax] + (int64_t)tt * L;
-            float Sa = a.w2[ax][tt] * D;
-#pragma unroll
-            for (int nu = 0; nu < L; ++nu) {
-                const float2 q = bc[nu];
-                const float mn = fmaf(q.x, m[ax][nu], q.y * D);
-                Sa += CENTRED ? m[ax][nu] : mn;
-                m[ax][nu] = mn;
-            }
-            S += Sa;
-        }
-        const float kappa = k0 * (1.0f + q0 * p0);
-        pp[idx] = p0 - a.dt * S / kappa;
-#pragma unroll
-        for (int ax = 0; ax < 2; ++ax)
-#pragma unroll
-            for (int nu = 0; nu < L; ++nu) psi[(int64_t)(ax * L + nu) * g.stride + idx] = m[ax][nu];
+        if (PF) cur = nxt;
     }
 }
 
-template <int L, bool CENTRED, int BX>
+template <int L>
+struct VRow {                 // everything the velocity sweep loads for one row
+    float pn, rn, kn, hp, hr, hk;   // window row j+4, rho/kappa0 row j+1, halos
+    float ux, uy;
+    int l;
+    float m[2][L];
+};
+
+template <int L, int BX>
+__device__ __forceinline__ void v_load_row(VRow<L> &r, const StepArgs &a, int i, int t, int x0, int j, bool live)
+{
+    const Geometry &g = a.geo;
+    r.pn = ldz(a.p, g, i, j + 4);
+    r.rn = ldz(a.rho, g, i, j + 1);
+    r.kn = ldz(a.kap, g, i, j + 1);
+    r.hp = t < 8 ? ldz(a.p, g, halo_x<BX>(t, x0), j + 1) : 0.0f;
+    r.hr = t == 0 ? ldz(a.rho, g, x0 + BX, j + 1) : 0.0f;
+    r.hk = t == 0 ? ldz(a.kap, g, x0 + BX, j + 1) : 0.0f;
+    const int64_t idx = g.origin + (int64_t)j * g.pitch + i;
+    if (live) {
+        r.ux = a.v[idx];
+        r.uy = a.v[g.stride + idx];
+        r.l = a.label ? (int)a.label[idx] : 0;
+#pragma unroll
+        for (int ax = 0; ax < 2; ++ax)
+#pragma unroll
+            for (int nu = 0; nu < L; ++nu) r.m[ax][nu] = a.psi1[(int64_t)(ax * L + nu) * g.stride + idx];
+    }
+}
+
+template <int L, bool CENTRED, int BX, bool PF>
 __global__ void __launch_bounds__(BX) velocity_sweep2d(const StepArgs a, int rows, int nbx, int nblocks)
 {
     const Geometry &g = a.geo;
@@ -296,14 +363,11 @@ __global__ void __launch_bounds__(BX) velocity_sweep2d(const StepArgs a, int row
     const int t = threadIdx.x;
     const int i = x0 + t;
     const int nx = g.n[0], ny = g.n[1];
-    const int64_t P = g.pitch;
+    const bool live = i < nx;
     const float *__restrict__ pp = a.p;
     float *__restrict__ vx = a.v;
     float *__restrict__ vy = a.v + g.stride;
     float *__restrict__ psi = a.psi1;
-    const float *__restrict__ rho = a.rho;
-    const float *__restrict__ kap = a.kap;
-    const uint8_t *__restrict__ lab = a.label;
 
     __shared__ float sp[4][BX + 8];     // p rows, column c <-> x0 - 4 + c
     __shared__ float sr[3][BX + 1];     // rho rows, column c <-> x0 + c
@@ -313,111 +377,347 @@ __global__ void __launch_bounds__(BX) velocity_sweep2d(const StepArgs a, int row
     float w[8];
     w[0] = 0.0f;
 #pragma unroll
-    for (int k = 1; k < 8; ++k) w[k] = ld2(pp, g, i, y0 - 4 + k);
+    for (int k = 1; k < 8; ++k) w[k] = ldz(pp, g, i, y0 - 4 + k);
 #pragma unroll
     for (int r = -1; r <= 0; ++r) {
-        sp[(y0 + r) & 3][t + 4] = ld2(pp, g, i, y0 + r);
-        if (t < 8) {
-            const int xc = t < 4 ? x0 - 4 + t : x0 + BX + (t - 4);
-            sp[(y0 + r) & 3][t < 4 ? t : BX + t] = ld2(pp, g, xc, y0 + r);
-        }
+        sp[(y0 + r) & 3][t + 4] = ldz(pp, g, i, y0 + r);
+        if (t < 8) sp[(y0 + r) & 3][halo_c<BX>(t)] = ldz(pp, g, halo_x<BX>(t, x0), y0 + r);
     }
-    sr[y0 % 3][t] = ld2(rho, g, i, y0);
-    sk[y0 % 3][t] = ld2(kap, g, i, y0);
+    sr[y0 % 3][t] = ldz(a.rho, g, i, y0);
+    sk[y0 % 3][t] = ldz(a.kap, g, i, y0);
     if (t == 0) {
-        sr[y0 % 3][BX] = ld2(rho, g, x0 + BX, y0);
-        sk[y0 % 3][BX] = ld2(kap, g, x0 + BX, y0);
+        sr[y0 % 3][BX] = ldz(a.rho, g, x0 + BX, y0);
+        sk[y0 % 3][BX] = ldz(a.kap, g, x0 + BX, y0);
     }
 
-    const int sxs = a.nb[0] > 0 ? max(max(a.nb[0] - i, i - (nx - 2 - a.nb[0])), 0) : 0;
+    const int sxs = max(max(a.nb[0] - i, i - (nx - 2 - a.nb[0])), 0);
     const int yend = min(y0 + rows, ny);
+    VRow<L> cur, nxt;
+    if (PF) v_load_row<L, BX>(cur, a, i, t, x0, y0, live);
     for (int j = y0; j < yend; ++j) {
-        const bool live = i < nx;
-        const int64_t idx = g.origin + (int64_t)j * P + i;
-        const float pn = ld2(pp, g, i, j + 4);
-        const float rn = ld2(rho, g, i, j + 1);
-        const float kn = ld2(kap, g, i, j + 1);
-        float hp = 0.0f, hr = 0.0f, hk = 0.0f;
-        if (t < 8) hp = ld2(pp, g, t < 4 ? x0 - 4 + t : x0 + BX + (t - 4), j + 1);
-        if (t == 0) {
-            hr = ld2(rho, g, x0 + BX, j + 1);
-            hk = ld2(kap, g, x0 + BX, j + 1);
-        }
-        float ux = 0.0f, uy = 0.0f;
-        float m[2][L];
-        int l = 0;
-        if (live) {
-            ux = vx[idx];
-            uy = vy[idx];
-            l = lab ? (int)lab[idx] : 0;
-#pragma unroll
-            for (int ax = 0; ax < 2; ++ax)
-#pragma unroll
-                for (int nu = 0; nu < L; ++nu) m[ax][nu] = psi[(int64_t)(ax * L + nu) * g.stride + idx];
-        }
+        if (!PF) v_load_row<L, BX>(cur, a, i, t, x0, j, live);
+        else if (j + 1 < yend) v_load_row<L, BX>(nxt, a, i, t, x0, j + 1, live);
 #pragma unroll
         for (int k = 0; k < 7; ++k) w[k] = w[k + 1];
-        w[7] = pn;
+        w[7] = cur.pn;
         sp[(j + 1) & 3][t + 4] = w[4];
-        if (t < 8) sp[(j + 1) & 3][t < 4 ? t : BX + t] = hp;
-        sr[(j + 1) % 3][t] = rn;
-        sk[(j + 1) % 3][t] = kn;
+        if (t < 8) sp[(j + 1) & 3][halo_c<BX>(t)] = cur.hp;
+        sr[(j + 1) % 3][t] = cur.rn;
+        sk[(j + 1) % 3][t] = cur.kn;
         if (t == 0) {
-            sr[(j + 1) % 3][BX] = hr;
-            sk[(j + 1) % 3][BX] = hk;
+            sr[(j + 1) % 3][BX] = cur.hr;
+            sk[(j + 1) % 3][BX] = cur.hk;
         }
+        lds_sync<BX>();
+        if (live) {
+            const int64_t idx = g.origin + (int64_t)j * g.pitch + i;
+            const float *r0 = sp[j & 3], *rp = sp[(j + 1) & 3], *rm = sp[(j + 3) & 3];
+            const float *rr0 = sr[j % 3], *kk0 = sk[j % 3];
+            // v_x at (i + 1/2, j)
+            if (i < nx - 1) {
+                float D = a.g[0] * (r0[t + 5] - r0[t + 4]);
+                D = fmaf(a.g[1], r0[t + 6] - r0[t + 3], D);
+                D = fmaf(a.g[2], r0[t + 7] - r0[t + 2], D);
+                D = fmaf(a.g[3], r0[t + 8] - r0[t + 1], D);
+                D = fmaf(a.g11, (rp[t + 5] - rp[t + 4]) + (rm[t + 5] - rm[t + 4]), D);
+                const int tt = sxs * a.n_labels + cur.l;
+                const float2 *__restrict__ bc = a.bc1[0] + (int64_t)tt * L;
+                float S = a.w1[0][tt] * D;
+#pragma unroll
+                for (int nu = 0; nu < L; ++nu) {
+                    const float2 q = bc[nu];
+                    const float mn = fmaf(q.x, cur.m[0][nu], q.y * D);
+                    S += CENTRED ? cur.m[0][nu] : mn;
+                    cur.m[0][nu] = mn;
+                }
+                const float pbar = 0.5f * (r0[t + 4] + r0[t + 5]);
+                const float rho_a = 0.5f * (rr0[t] + rr0[t + 1]);
+                const float kap_a = 0.5f * (kk0[t] + kk0[t + 1]);
+                vx[idx] = cur.ux - a.dt * S / (rho_a * (1.0f + kap_a * pbar));
+#pragma unroll
+                for (int nu = 0; nu < L; ++nu) psi[(int64_t)nu * g.stride + idx] = cur.m[0][nu];
+            }
+            // v_y at (i, j + 1/2)
+            if (j < ny - 1) {
+                const int sys = max(max(a.nb[1] - j, j - (ny - 2 - a.nb[1])), 0);
+                float D = a.g[0] * (w[4] - w[3]);
+                D = fmaf(a.g[1], w[5] - w[2], D);
+                D = fmaf(a.g[2], w[6] - w[1], D);
+                D = fmaf(a.g[3], w[7] - w[0], D);
+                D = fmaf(a.g11, (rp[t + 5] - r0[t + 5]) + (rp[t + 3] - r0[t + 3]), D);
+                const int tt = sys * a.n_labels + cur.l;
+                const float2 *__restrict__ bc = a.bc1[1] + (int64_t)tt * L;
+                float S = a.w1[1][tt] * D;
+#pragma unroll
+                for (int nu = 0; nu < L; ++nu) {
+                    const float2 q = bc[nu];
+                    const float mn = fmaf(q.x, cur.m[1][nu], q.y * D);
+                    S += CENTRED ? cur.m[1][nu] : mn;
+                    cur.m[1][nu] = mn;
+                }
+                const float pbar = 0.5f * (w[3] + w[4]);
+                const float rho_a = 0.5f * (rr0[t] + sr[(j + 1) % 3][t]);
+                const float kap_a = 0.5f * (kk0[t] + sk[(j + 1) % 3][t]);
+                vy[idx] = cur.uy - a.dt * S / (rho_a * (1.0f + kap_a * pbar));
+#pragma unroll
+                for (int nu = 0; nu < L; ++nu) psi[(int64_t)(L + nu) * g.stride + idx] = cur.m[1][nu];
+            }
+        }
+        if (PF) cur = nxt;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 3D sweep kernels.  A block of BX x BY threads owns a BX x BY column tile
+// and walks `rows` planes in +z.  The z-stencil field of each column sits in
+// an 8-plane register window; planes of the x/y-stencil fields (with their
+// halos) are staged cooperatively into LDS rings, one barrier per plane.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ float ldz3(const float *__restrict__ f, const Geometry &g, int x, int y, int z)
+{
+    const bool in = (unsigned)x < (unsigned)g.n[0] && (unsigned)y < (unsigned)g.n[1] &&
+                    (unsigned)z < (unsigned)g.n[2];
+    const int64_t o = in ? g.origin + (int64_t)z * g.plane + (int64_t)y * g.pitch + x
+                         : g.origin - g.plane - g.pitch - 1;
+    return f[o];
+}
+
+// Stage the (H x W) window of plane z whose (0, 0) is (xs, ys) into LDS.
+template <int W, int H, int NT>
+__device__ __forceinline__ void stage(float *dst, const float *__restrict__ f, const Geometry &g, int xs, int ys,
+                                      int z, int tid)
+{
+#pragma unroll
+    for (int e = tid; e < W * H; e += NT) {
+        const int r = e / W, c = e - r * W;
+        dst[e] = ldz3(f, g, xs + c, ys + r, z);
+    }
+}
+
+template <int L, bool CENTRED, int BX, int BY>
+__global__ void __launch_bounds__(BX *BY) pressure_sweep3d(const StepArgs a, int rows, int nbx, int nby, int nblocks)
+{
+    constexpr int NT = BX * BY;
+    constexpr int XW = BX + 8, XH = BY + 2;     // v_x tile: x halo 4, y halo 1
+    constexpr int YW = BX + 2, YH = BY + 8;     // v_y tile: x halo 1, y halo 4
+    constexpr int ZW = BX + 2, ZH = BY + 2;     // v_z tile: halo 1
+    const Geometry &g = a.geo;
+    const int tile = tile_of_block(blockIdx.x, nblocks);
+    const int tx_ = tile % nbx, rest = tile / nbx;
+    const int x0 = tx_ * BX, y0 = (rest % nby) * BY, z0 = (rest / nby) * rows;
+    const int tid = threadIdx.x;
+    const int tx = tid % BX, ty = tid / BX;
+    const int i = x0 + tx, j = y0 + ty;
+    const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+    const bool live = i < nx && j < ny;
+    const float *__restrict__ vx = a.v;
+    const float *__restrict__ vy = a.v + g.stride;
+    const float *__restrict__ vz = a.v + 2 * g.stride;
+
+    __shared__ float sx[4][XH * XW];
+    __shared__ float sy[4][YH * YW];
+    __shared__ float sz[3][ZH * ZW];
+
+    float w[8];
+    w[0] = 0.0f;
+#pragma unroll
+    for (int q = 1; q < 8; ++q) w[q] = ldz3(vz, g, i, j, z0 - 5 + q);
+#pragma unroll
+    for (int r = -1; r <= 0; ++r) {
+        stage<XW, XH, NT>(sx[(z0 + r) & 3], vx, g, x0 - 4, y0 - 1, z0 + r, tid);
+        stage<YW, YH, NT>(sy[(z0 + r) & 3], vy, g, x0 - 1, y0 - 4, z0 + r, tid);
+    }
+    stage<ZW, ZH, NT>(sz[(z0 + 2) % 3], vz, g, x0 - 1, y0 - 1, z0 - 1, tid);
+
+    const int s0 = max(max(a.nb[0] - i, i - (nx - 1 - a.nb[0])), 0);
+    const int s1 = max(max(a.nb[1] - j, j - (ny - 1 - a.nb[1])), 0);
+    const int zend = min(z0 + rows, nz);
+    for (int k = z0; k < zend; ++k) {
+        stage<XW, XH, NT>(sx[(k + 1) & 3], vx, g, x0 - 4, y0 - 1, k + 1, tid);
+        stage<YW, YH, NT>(sy[(k + 1) & 3], vy, g, x0 - 1, y0 - 4, k + 1, tid);
+        stage<ZW, ZH, NT>(sz[k % 3], vz, g, x0 - 1, y0 - 1, k, tid);
+        const float vzn = ldz3(vz, g, i, j, k + 3);
+        const int64_t idx = g.origin + (int64_t)k * g.plane + (int64_t)j * g.pitch + i;
+        float p0 = 0.0f, k0 = 1.0f, q0 = 0.0f;
+        float m[3][L];
+        int l = 0;
+        if (live) {
+            p0 = a.p[idx];
+            k0 = a.kap[idx];
+            q0 = a.nlq[idx];
+            l = a.label ? (int)a.label[idx] : 0;
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax)
+#pragma unroll
+                for (int nu = 0; nu < L; ++nu) m[ax][nu] = a.psi2[(int64_t)(ax * L + nu) * g.stride + idx];
+        }
+#pragma unroll
+        for (int q = 0; q < 7; ++q) w[q] = w[q + 1];
+        w[7] = vzn;
         __syncthreads();
-        if (!live) continue;
-        const float *r0 = sp[j & 3], *rp = sp[(j + 1) & 3], *rm = sp[(j + 3) & 3];
-        const float *rr0 = sr[j % 3], *kk0 = sk[j % 3];
-        const int sys = a.nb[1] > 0 ? max(max(a.nb[1] - j, j - (ny - 2 - a.nb[1])), 0) : 0;
-        // v_x at (i + 1/2, j)
-        if (i < nx - 1) {
-            float D = a.g[0] * (r0[t + 5] - r0[t + 4]);
-            D = fmaf(a.g[1], r0[t + 6] - r0[t + 3], D);
-            D = fmaf(a.g[2], r0[t + 7] - r0[t + 2], D);
-            D = fmaf(a.g[3], r0[t + 8] - r0[t + 1], D);
-            D = fmaf(a.g11, (rp[t + 5] - rp[t + 4]) + (rm[t + 5] - rm[t + 4]), D);
-            const int tt = sxs * a.n_labels + l;
-            const float2 *__restrict__ bc = a.bc1[0] + (int64_t)tt * L;
-            float S = a.w1[0][tt] * D;
+        if (live) {
+            const float *X0 = sx[k & 3], *Xp = sx[(k + 1) & 3], *Xm = sx[(k + 3) & 3];
+            const int cx = (ty + 1) * XW + tx + 4;          // own sample in the v_x tile
+            float Dx = a.g[0] * (X0[cx] - X0[cx - 1]);
+            Dx = fmaf(a.g[1], X0[cx + 1] - X0[cx - 2], Dx);
+            Dx = fmaf(a.g[2], X0[cx + 2] - X0[cx - 3], Dx);
+            Dx = fmaf(a.g[3], X0[cx + 3] - X0[cx - 4], Dx);
+            Dx = fmaf(a.g11, ((X0[cx + XW] - X0[cx + XW - 1]) + (X0[cx - XW] - X0[cx - XW - 1])) +
+                                 ((Xp[cx] - Xp[cx - 1]) + (Xm[cx] - Xm[cx - 1])), Dx);
+            const float *Y0 = sy[k & 3], *Yp = sy[(k + 1) & 3], *Ym = sy[(k + 3) & 3];
+            const int cy = (ty + 4) * YW + tx + 1;
+            float Dy = a.g[0] * (Y0[cy] - Y0[cy - YW]);
+            Dy = fmaf(a.g[1], Y0[cy + YW] - Y0[cy - 2 * YW], Dy);
+            Dy = fmaf(a.g[2], Y0[cy + 2 * YW] - Y0[cy - 3 * YW], Dy);
+            Dy = fmaf(a.g[3], Y0[cy + 3 * YW] - Y0[cy - 4 * YW], Dy);
+            Dy = fmaf(a.g11, ((Y0[cy + 1] - Y0[cy + 1 - YW]) + (Y0[cy - 1] - Y0[cy - 1 - YW])) +
+                                 ((Yp[cy] - Yp[cy - YW]) + (Ym[cy] - Ym[cy - YW])), Dy);
+            const float *Z0 = sz[k % 3], *Zm = sz[(k + 2) % 3];
+            const int cz = (ty + 1) * ZW + tx + 1;
+            float Dz = a.g[0] * (w[4] - w[3]);
+            Dz = fmaf(a.g[1], w[5] - w[2], Dz);
+            Dz = fmaf(a.g[2], w[6] - w[1], Dz);
+            Dz = fmaf(a.g[3], w[7] - w[0], Dz);
+            Dz = fmaf(a.g11, ((Z0[cz + 1] - Zm[cz + 1]) + (Z0[cz - 1] - Zm[cz - 1])) +
+                                 ((Z0[cz + ZW] - Zm[cz + ZW]) + (Z0[cz - ZW] - Zm[cz - ZW])), Dz);
+            const int s2 = max(max(a.nb[2] - k, k - (nz - 1 - a.nb[2])), 0);
+            float S = 0.0f;
 #pragma unroll
-            for (int nu = 0; nu < L; ++nu) {
-                const float2 q = bc[nu];
-                const float mn = fmaf(q.x, m[0][nu], q.y * D);
-                S += CENTRED ? m[0][nu] : mn;
-                m[0][nu] = mn;
+            for (int ax = 0; ax < 3; ++ax) {
+                const float D = ax == 0 ? Dx : (ax == 1 ? Dy : Dz);
+                const int tt = (ax == 0 ? s0 : (ax == 1 ? s1 : s2)) * a.n_labels + l;
+                const float2 *__restrict__ bc = a.bc2[ax] + (int64_t)tt * L;
+                float Sa = a.w2[ax][tt] * D;
+#pragma unroll
+                for (int nu = 0; nu < L; ++nu) {
+                    const float2 q = bc[nu];
+                    const float mn = fmaf(q.x, m[ax][nu], q.y * D);
+                    Sa += CENTRED ? m[ax][nu] : mn;
+                    m[ax][nu] = mn;
+                }
+                S += Sa;
             }
-            const float pbar = 0.5f * (r0[t + 4] + r0[t + 5]);
-            const float rho_a = 0.5f * (rr0[t] + rr0[t + 1]);
-            const float kap_a = 0.5f * (kk0[t] + kk0[t + 1]);
-            vx[idx] = ux - a.dt * S / (rho_a * (1.0f + kap_a * pbar));
+            const float kappa = k0 * (1.0f + q0 * p0);
+            a.p[idx] = p0 - a.dt * S / kappa;
 #pragma unroll
-            for (int nu = 0; nu < L; ++nu) psi[(int64_t)nu * g.stride + idx] = m[0][nu];
+            for (int ax = 0; ax < 3; ++ax)
+#pragma unroll
+                for (int nu = 0; nu < L; ++nu) a.psi2[(int64_t)(ax * L + nu) * g.stride + idx] = m[ax][nu];
         }
-        // v_y at (i, j + 1/2)
-        if (j < ny - 1) {
-            float D = a.g[0] * (w[4] - w[3]);
-            D = fmaf(a.g[1], w[5] - w[2], D);
-            D = fmaf(a.g[2], w[6] - w[1], D);
-            D = fmaf(a.g[3], w[7] - w[0], D);
-            D = fmaf(a.g11, (rp[t + 5] - r0[t + 5]) + (rp[t + 3] - r0[t + 3]), D);
-            const int tt = sys * a.n_labels + l;
-            const float2 *__restrict__ bc = a.bc1[1] + (int64_t)tt * L;
-            float S = a.w1[1][tt] * D;
+    }
+}
+
+template <int L, bool CENTRED, int BX, int BY>
+__global__ void __launch_bounds__(BX *BY) velocity_sweep3d(const StepArgs a, int rows, int nbx, int nby, int nblocks)
+{
+    constexpr int NT = BX * BY;
+    constexpr int PW = BX + 8, PH = BY + 8;     // p tile: halo 4 (x0-4.., y0-4..)
+    constexpr int RW = BX + 1, RH = BY + 1;     // rho / kappa0 tiles: +1 halo
+    const Geometry &g = a.geo;
+    const int tile = tile_of_block(blockIdx.x, nblocks);
+    const int tx_ = tile % nbx, rest = tile / nbx;
+    const int x0 = tx_ * BX, y0 = (rest % nby) * BY, z0 = (rest / nby) * rows;
+    const int tid = threadIdx.x;
+    const int tx = tid % BX, ty = tid / BX;
+    const int i = x0 + tx, j = y0 + ty;
+    const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+    const bool live = i < nx && j < ny;
+    const float *__restrict__ pp = a.p;
+
+    __shared__ float sp[4][PH * PW];
+    __shared__ float sr[3][RH * RW];
+    __shared__ float sk[3][RH * RW];
+
+    float w[8];
+    w[0] = 0.0f;
 #pragma unroll
-            for (int nu = 0; nu < L; ++nu) {
-                const float2 q = bc[nu];
-                const float mn = fmaf(q.x, m[1][nu], q.y * D);
-                S += CENTRED ? m[1][nu] : mn;
-                m[1][nu] = mn;
+    for (int q = 1; q < 8; ++q) w[q] = ldz3(pp, g, i, j, z0 - 4 + q);
+#pragma unroll
+    for (int r = -1; r <= 0; ++r) stage<PW, PH, NT>(sp[(z0 + r) & 3], pp, g, x0 - 4, y0 - 4, z0 + r, tid);
+    stage<RW, RH, NT>(sr[z0 % 3], a.rho, g, x0, y0, z0, tid);
+    stage<RW, RH, NT>(sk[z0 % 3], a.kap, g, x0, y0, z0, tid);
+
+    const int s0 = max(max(a.nb[0] - i, i - (nx - 2 - a.nb[0])), 0);
+    const int s1 = max(max(a.nb[1] - j, j - (ny - 2 - a.nb[1])), 0);
+    const int zend = min(z0 + rows, nz);
+    for (int k = z0; k < zend; ++k) {
+        stage<PW, PH, NT>(sp[(k + 1) & 3], pp, g, x0 - 4, y0 - 4, k + 1, tid);
+        stage<RW, RH, NT>(sr[(k + 1) % 3], a.rho, g, x0, y0, k + 1, tid);
+        stage<RW, RH, NT>(sk[(k + 1) % 3], a.kap, g, x0, y0, k + 1, tid);
+        const float pn = ldz3(pp, g, i, j, k + 4);
+        const int64_t idx = g.origin + (int64_t)k * g.plane + (int64_t)j * g.pitch + i;
+        float u[3] = {0.0f, 0.0f, 0.0f};
+        float m[3][L];
+        int l = 0;
+        if (live) {
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax) u[ax] = a.v[(int64_t)ax * g.stride + idx];
+            l = a.label ? (int)a.label[idx] : 0;
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax)
+#pragma unroll
+                for (int nu = 0; nu < L; ++nu) m[ax][nu] = a.psi1[(int64_t)(ax * L + nu) * g.stride + idx];
+        }
+#pragma unroll
+        for (int q = 0; q < 7; ++q) w[q] = w[q + 1];
+        w[7] = pn;
+        __syncthreads();
+        if (live) {
+            const float *P0 = sp[k & 3], *Pp = sp[(k + 1) & 3], *Pm = sp[(k + 3) & 3];
+            const float *R0 = sr[k % 3], *Rp = sr[(k + 1) % 3], *K0 = sk[k % 3], *Kp = sk[(k + 1) % 3];
+            const int c = (ty + 4) * PW + tx + 4;           // own sample in the p tile
+            const int cr = ty * RW + tx;                    // own sample in the rho tile
+            const int s2 = max(max(a.nb[2] - k, k - (nz - 2 - a.nb[2])), 0);
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax) {
+                if ((ax == 0 && i == nx - 1) || (ax == 1 && j == ny - 1) || (ax == 2 && k == nz - 1)) continue;
+                float D, pbar, rho_a, kap_a;
+                if (ax == 0) {
+                    D = a.g[0] * (P0[c + 1] - P0[c]);
+                    D = fmaf(a.g[1], P0[c + 2] - P0[c - 1], D);
+                    D = fmaf(a.g[2], P0[c + 3] - P0[c - 2], D);
+                    D = fmaf(a.g[3], P0[c + 4] - P0[c - 3], D);
+                    D = fmaf(a.g11, ((P0[c + 1 + PW] - P0[c + PW]) + (P0[c + 1 - PW] - P0[c - PW])) +
+                                        ((Pp[c + 1] - Pp[c]) + (Pm[c + 1] - Pm[c])), D);
+                    pbar = 0.5f * (P0[c] + P0[c + 1]);
+                    rho_a = 0.5f * (R0[cr] + R0[cr + 1]);
+                    kap_a = 0.5f * (K0[cr] + K0[cr + 1]);
+                } else if (ax == 1) {
+                    D = a.g[0] * (P0[c + PW] - P0[c]);
+                    D = fmaf(a.g[1], P0[c + 2 * PW] - P0[c - PW], D);
+                    D = fmaf(a.g[2], P0[c + 3 * PW] - P0[c - 2 * PW], D);
+                    D = fmaf(a.g[3], P0[c + 4 * PW] - P0[c - 3 * PW], D);
+                    D = fmaf(a.g11, ((P0[c + PW + 1] - P0[c + 1]) + (P0[c + PW - 1] - P0[c - 1])) +
+                                        ((Pp[c + PW] - Pp[c]) + (Pm[c + PW] - Pm[c])), D);
+                    pbar = 0.5f * (P0[c] + P0[c + PW]);
+                    rho_a = 0.5f * (R0[cr] + R0[cr + RW]);
+                    kap_a = 0.5f * (K0[cr] + K0[cr + RW]);
+                } else {
+                    D = a.g[0] * (w[4] - w[3]);
+                    D = fmaf(a.g[1], w[5] - w[2], D);
+                    D = fmaf(a.g[2], w[6] - w[1], D);
+                    D = fmaf(a.g[3], w[7] - w[0], D);
+                    D = fmaf(a.g11, ((Pp[c + 1] - P0[c + 1]) + (Pp[c - 1] - P0[c - 1])) +
+                                        ((Pp[c + PW] - P0[c + PW]) + (Pp[c - PW] - P0[c - PW])), D);
+                    pbar = 0.5f * (w[3] + w[4]);
+                    rho_a = 0.5f * (R0[cr] + Rp[cr]);
+                    kap_a = 0.5f * (K0[cr] + Kp[cr]);
+                }
+                const int tt = (ax == 0 ? s0 : (ax == 1 ? s1 : s2)) * a.n_labels + l;
+                const float2 *__restrict__ bc = a.bc1[ax] + (int64_t)tt * L;
+                float S = a.w1[ax][tt] * D;
+#pragma unroll
+                for (int nu = 0; nu < L; ++nu) {
+                    const float2 q = bc[nu];
+                    const float mn = fmaf(q.x, m[ax][nu], q.y * D);
+                    S += CENTRED ? m[ax][nu] : mn;
+                    m[ax][nu] = mn;
+                }
+                a.v[(int64_t)ax * g.stride + idx] = u[ax] - a.dt * S / (rho_a * (1.0f + kap_a * pbar));
+#pragma unroll
+                for (int nu = 0; nu < L; ++nu) a.psi1[(int64_t)(ax * L + nu) * g.stride + idx] = m[ax][nu];
             }
-            const float pbar = 0.5f * (w[3] + w[4]);
-            const float rho_a = 0.5f * (rr0[t] + sr[(j + 1) % 3][t]);
-            const float kap_a = 0.5f * (kk0[t] + sk[(j + 1) % 3][t]);
-            vy[idx] = uy - a.dt * S / (rho_a * (1.0f + kap_a * pbar));
-#pragma unroll
-            for (int nu = 0; nu < L; ++nu) psi[(int64_t)(L + nu) * g.stride + idx] = m[1][nu];
         }
     }
 }
@@ -474,7 +774,7 @@ __global__ void check_kernel(const float *p, const Geometry g, float limit, int 
     if (!(fabsf(v) <= limit)) atomicOr(flag, 1);     // also catches NaN
 }
 
-template <int L, bool C>
+template <int L, bool C, bool PF>
 hipError_t launch_sweep(const StepArgs &a, bool pressure, const KernelConfig &kc, hipStream_t st)
 {
     const int nbx = (a.geo.n[0] + kc.bx - 1) / kc.bx;
@@ -483,15 +783,38 @@ hipError_t launch_sweep(const StepArgs &a, bool pressure, const KernelConfig &kc
 #define FW2_SWEEP(BXV)                                                                                  \
     if (kc.bx == BXV) {                                                                                 \
         if (pressure)                                                                                   \
-            hipLaunchKernelGGL((pressure_sweep2d<L, C, BXV>), dim3(nblocks), dim3(BXV), 0, st, a, kc.rows, nbx, nblocks); \
+            hipLaunchKernelGGL((pressure_sweep2d<L, C, BXV, PF>), dim3(nblocks), dim3(BXV), 0, st, a, kc.rows, nbx, nblocks); \
         else                                                                                            \
-            hipLaunchKernelGGL((velocity_sweep2d<L, C, BXV>), dim3(nblocks), dim3(BXV), 0, st, a, kc.rows, nbx, nblocks); \
+            hipLaunchKernelGGL((velocity_sweep2d<L, C, BXV, PF>), dim3(nblocks), dim3(BXV), 0, st, a, kc.rows, nbx, nblocks); \
         return hipGetLastError();                                                                       \
     }
     FW2_SWEEP(64)
     FW2_SWEEP(128)
     FW2_SWEEP(256)
 #undef FW2_SWEEP
+    return hipErrorInvalidValue;
+}
+
+template <int L, bool C>
+hipError_t launch_sweep3(const StepArgs &a, bool pressure, const KernelConfig &kc, hipStream_t st)
+{
+#define FW2_SWEEP3(BXV, BYV)                                                                            \
+    if (kc.bx == BXV) {                                                                                 \
+        const int nbx = (a.geo.n[0] + BXV - 1) / BXV, nby = (a.geo.n[1] + BYV - 1) / BYV;                \
+        const int nbz = (a.geo.n[2] + kc.rows - 1) / kc.rows;                                           \
+        const int nblocks = nbx * nby * nbz;                                                            \
+        if (pressure)                                                                                   \
+            hipLaunchKernelGGL((pressure_sweep3d<L, C, BXV, BYV>), dim3(nblocks), dim3(BXV * BYV), 0, st, \
+                               a, kc.rows, nbx, nby, nblocks);                                          \
+        else                                                                                            \
+            hipLaunchKernelGGL((velocity_sweep3d<L, C, BXV, BYV>), dim3(nblocks), dim3(BXV * BYV), 0, st, \
+                               a, kc.rows, nbx, nby, nblocks);                                          \
+        return hipGetLastError();                                                                       \
+    }
+    FW2_SWEEP3(32, 16)
+    FW2_SWEEP3(64, 8)
+    FW2_SWEEP3(16, 16)
+#undef FW2_SWEEP3
     return hipErrorInvalidValue;
 }
 
@@ -516,9 +839,14 @@ hipError_t launch_v(const StepArgs &a, hipStream_t st)
 template <bool P, int NDIM, int L>
 hipError_t dispatch_scheme(const StepArgs &a, int scheme, const KernelConfig &kc, hipStream_t st)
 {
-    if (NDIM == 2 && kc.variant == 1) {
-        if (scheme == 0) return launch_sweep<L, false>(a, P, kc, st);
-        return launch_sweep<L, true>(a, P, kc, st);
+    if (NDIM == 3 && kc.variant == 1) {
+        if (scheme == 0) return launch_sweep3<L, false>(a, P, kc, st);
+        return launch_sweep3<L, true>(a, P, kc, st);
+    }
+    if (NDIM == 2 && (kc.variant == 1 || kc.variant == 2)) {
+        const bool pf = kc.variant == 2;
+        if (scheme == 0) return pf ? launch_sweep<L, false, true>(a, P, kc, st) : launch_sweep<L, false, false>(a, P, kc, st);
+        return pf ? launch_sweep<L, true, true>(a, P, kc, st) : launch_sweep<L, true, false>(a, P, kc, st);
     }
     if (scheme == 0) return P ? launch_p<NDIM, L, false>(a, st) : launch_v<NDIM, L, false>(a, st);
     return P ? launch_p<NDIM, L, true>(a, st) : launch_v<NDIM, L, true>(a, st);

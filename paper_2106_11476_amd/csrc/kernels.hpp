@@ -63,7 +63,10 @@ struct SparseArgs {
 // Kernel variant and tile shape.  variant 0: one thread per point over a
 // (64 x 8) tile, every stencil tap a cached global load (any ndim).
 // variant 1 (2D): row sweeps of `bx` columns x `rows` rows with a register
-// window along y and LDS rings along x.
+// window along y and LDS rings along x; variant 2: the same with the next
+// row's loads issued before the current row is computed.  variant 1 (3D):
+// plane sweeps of a column tile (32x16, 64x8 or 16x16 for bx = 32, 64, 16)
+// over `rows` planes with a register window along z and LDS plane rings.
 struct KernelConfig {
     int variant;
     int bx;

@@ -175,6 +175,16 @@ def test_3d_point_source():
     compare(f, tr, ref, rtr, "3d point", prob=prob)
 
 
+def test_skull_3d_small_cube():
+    """The 3D transcranial recipe (shell, porosity noise, two labels, focused
+    cap source, axis receivers) on a 96^3 cube with 12-cell layers."""
+    prob = W.skull_3d(n=96, nb=12, ntr=9, n_steps=260)
+    _say("skull_3d 96^3 L=2 260 steps")
+    f, tr, _ = gpu_run(prob, prob.n_steps)
+    ref, rtr = oracle_run(prob, prob.n_steps)
+    compare(f, tr, ref, rtr, "skull_3d_96", prob=prob)
+
+
 # ---------------------------------------------------------- edge cases ---
 
 def test_degenerate_grids():
@@ -286,7 +296,22 @@ def test_kernel_timing_counts_launches():
 
 # ------------------------------------------------- kernel variants / tiles ---
 
-@pytest.mark.parametrize("config", ["0,64,16", "1,64,16", "1,128,7", "1,256,33", "1,64,1"])
+@pytest.mark.parametrize("config", ["0,32,16", "1,32,16", "1,64,5", "1,32,1", "1,16,7"])
+@pytest.mark.parametrize("shape,L,scheme", [((37, 21, 19), 2, 1), ((70, 33, 24), 3, 0), ((16, 16, 40), 1, 1)])
+def test_3d_kernel_variants_match_oracle(monkeypatch, config, shape, L, scheme):
+    """3D plane-sweep tiles (32x16 and 64x8 columns, ragged in every axis,
+    one-plane tiles) and the generic kernel give oracle results."""
+    monkeypatch.setenv("FW2_KERNEL_CONFIG", config)
+    prob = W.random_medium(shape, L, 3, seed=9, nb=5, ntr=3)
+    prob.relax_scheme = scheme
+    st = _state(prob, 17)
+    _say("3d variant", config, shape, "L", L, "scheme", scheme)
+    f, tr, _ = gpu_run(prob, 8, state=st)
+    ref, rtr = oracle_run(prob, 8, state=st)
+    compare(f, tr, ref, rtr, "3d variant %s %s" % (config, shape), prob=prob)
+
+
+@pytest.mark.parametrize("config", ["0,64,16", "1,64,16", "1,128,7", "1,256,33", "1,64,1", "2,64,8", "2,256,5"])
 @pytest.mark.parametrize("shape,L,scheme", [((70, 45), 2, 1), ((257, 131), 4, 1), ((131, 90), 3, 0)])
 def test_kernel_variants_match_oracle(monkeypatch, config, shape, L, scheme):
     """Every kernel variant and tile shape (including tiles that overhang

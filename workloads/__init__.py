@@ -282,3 +282,88 @@ def abdominal_2d(nx=4096, ny=2048, seed=2, n_steps=12000, ppw=12, f0=3e6, cfl=0.
     centres = x0 + np.arange(n_el) * pitch + width // 2
     prob.rcv_idx = prob.flat(centres, np.full_like(centres, ey))
     return prob
+
+
+# ---------------------------------------------------------------------------
+# Workload 3: 3D transcranial-like medium, L = 2
+# ---------------------------------------------------------------------------
+
+def skull_3d(n=1024, nb=48, ntr=36, seed=3, n_steps=4000, ppw=12, f0=1e6, cfl=0.4, n_rcv=1024):
+    """Cube of n^3 points including nb-cell layers: brain-like background
+    (c 1540, rho 1040, beta 4; Table 2 tuple), a curved bone-like shell
+    (thickness 4-8 cells = 0.5-1 mm at 12 ppw / 1 MHz; c 2800, rho 1900,
+    alpha0 8 dB/MHz/cm fitted with two mechanisms; +-10% porosity noise on c
+    and rho) between a focused spherical-cap source (aperture 0.49 of the
+    domain, radius of curvature equal to it, apex 8 cells below the top
+    layer) and its focus; receivers on the focal axis.  The geometry scales
+    with n (same recipe on smaller cubes for parity tests).  z is the depth
+    (slowest) axis."""
+    rng = np.random.default_rng(seed)
+    h = grid_spacing(1540.0, f0, ppw)
+    Ldom = n * h
+    grid = (n, n, n)
+    c = np.full(grid, 1540.0, np.float32)
+    rho = np.full(grid, 1040.0, np.float32)
+    beta = np.full(grid, 4.0, np.float32)
+    label = np.zeros(grid, np.uint8)
+    ctr = (n - 1) / 2.0
+    apex = nb + 8
+    Rcurv = 0.49 * n                        # cells
+    aper = 0.245 * n                        # aperture radius, cells
+    zf = apex + Rcurv                       # geometric focus on the axis
+    # shell: sphere about a point below the focus, upper part only
+    R_sk = 0.30 * n
+    zc = zf + 0.05 * n
+    ph = rng.uniform(0, 2 * np.pi, 4)
+    km = rng.normal(0, 1, (6, 3))
+    km = km / np.linalg.norm(km, axis=1, keepdims=True) * rng.uniform(0.15, 0.6, (6, 1))   # rad / cell
+    pm = rng.uniform(0, 2 * np.pi, 6)
+    am = rng.uniform(0.5, 1.0, 6)
+    am = am / am.sum()
+    yy, xx = np.mgrid[0:n, 0:n].astype(np.float32)
+    for z in range(n):
+        dz = z - zc
+        if dz > 0:
+            continue
+        r = np.sqrt((xx - ctr) ** 2 + (yy - ctr) ** 2 + dz * dz)
+        th = np.arctan2(yy - ctr, xx - ctr)
+        el = np.arccos(np.clip(-dz / np.maximum(r, 1e-6), -1, 1))
+        thick = 6.0 + 2.0 * np.sin(3 * th + ph[0]) * np.cos(4 * el + ph[1])
+        m = (r >= R_sk) & (r <= R_sk + thick)
+        if not m.any():
+            continue
+        noise = np.zeros(int(m.sum()), np.float32)
+        px, py = xx[m], yy[m]
+        for q in range(6):
+            noise += am[q] * np.sin(km[q, 0] * px + km[q, 1] * py + km[q, 2] * z + pm[q])
+        c[z][m] = (2800.0 * (1.0 + 0.1 * noise)).astype(np.float32)
+        rho[z][m] = (1900.0 * (1.0 + 0.1 * noise)).astype(np.float32)
+        label[z][m] = 1
+    dt = cfl * h / float(c.max())
+    rows = [TABLE2_ROW, tissue_row(8.0, 1.0, 2, 1e6)]
+    prob = Problem(shape=(n, n, n), h=h, dt=dt, n_relax=2, c=c, rho=rho, beta=beta,
+                   relax_table=np.asarray(rows, np.float64), label=label,
+                   bound_cells=(nb,) * 3, trans_cells=(ntr,) * 3, n_steps=n_steps,
+                   name="skull_3d_%d" % n)
+    # focused spherical cap: voxels within half a cell of the sphere of radius
+    # Rcurv about the focus, inside the aperture, above the focus
+    zs = np.arange(apex, int(np.ceil(zf)))
+    pts = []
+    for z in zs:
+        dz = z - zf
+        rho_xy2 = Rcurv * Rcurv - dz * dz
+        if rho_xy2 <= 0:
+            continue
+        r = np.sqrt((xx - ctr) ** 2 + (yy - ctr) ** 2 + dz * dz)
+        m = (np.abs(r - Rcurv) <= 0.5) & ((xx - ctr) ** 2 + (yy - ctr) ** 2 <= aper * aper)
+        if m.any():
+            pts.append(prob.flat(xx[m].astype(np.int64), yy[m].astype(np.int64), np.full(int(m.sum()), z)))
+    prob.src_idx = np.unique(np.concatenate(pts)).astype(np.int64)
+    prob.src_sig = np.zeros(prob.src_idx.size, np.int32)
+    prob.src_w = np.ones(prob.src_idx.size, np.float32)
+    nt = pulse_length(dt, f0, 3)
+    prob.signals = gaussian_pulse(nt, dt, f0, 3, amp=1e5)[None, :]
+    zr = np.unique(np.round(np.linspace(apex + 2, n - nb - 1, n_rcv)).astype(np.int64))
+    ci = int(round(ctr))
+    prob.rcv_idx = prob.flat(np.full(zr.size, ci), np.full(zr.size, ci), zr)
+    return prob
