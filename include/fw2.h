@@ -162,6 +162,36 @@ fw2_status fw2_get_kernel_timing(fw2_domain *dom, double ms[2], int64_t count[2]
  * below limit in magnitude; FW2_E_UNSTABLE otherwise. */
 fw2_status fw2_check_finite(fw2_domain *dom, float limit);
 
+/* ---- Batched stepping of many 2D domains (continuous batching) ----------
+ * A batch advances several resident 2D domains of any sizes, L and memory
+ * scheme with one launch per phase: blocks of a fixed grid walk the tiles of
+ * every active domain (the per-tile arithmetic is the single-domain sweep's,
+ * so results are bitwise those of stepping each domain alone).  Each domain
+ * stops by itself when its step counter reaches its own n_steps, so domains
+ * with different step counts share step loops; the loop is captured as a HIP
+ * graph that does not depend on which domains are active.
+ *   fw2_batch_workspace_bytes: device bytes of the batch table for up to
+ *     max_domains (1..64) domains; the caller allocates them (256-byte
+ *     aligned) and keeps them alive while the batch exists.
+ *   fw2_batch_set_domains: replaces the active set (synchronises the batch
+ *     stream).  Every domain must be 2D, created on the same device, and at
+ *     step < n_steps[k]; a domain that leaves the set gets its step counter
+ *     back (fw2_current_step stays exact).  n = 0 empties the batch.
+ *   fw2_batch_step: n steps of every active domain, asynchronously on the
+ *     batch stream (the domains' own streams are not used meanwhile).
+ *   fw2_batch_set_tile: tile of the batched sweep, cols = 64 or 256 columns by
+ *     rows >= 1 rows; only while the batch is empty.
+ * Errors: FW2_E_INVALID for bad arguments, FW2_E_UNSUPPORTED for 3D domains,
+ * FW2_E_HIP for runtime failures. */
+typedef struct fw2_batch fw2_batch;
+fw2_status fw2_batch_workspace_bytes(int32_t max_domains, uint64_t *bytes);
+fw2_status fw2_batch_create(int32_t max_domains, void *dev_workspace, uint64_t workspace_bytes,
+                            void *stream, fw2_batch **out);
+fw2_status fw2_batch_set_domains(fw2_batch *b, int32_t n, fw2_domain *const *domains, const int64_t *n_steps);
+fw2_status fw2_batch_step(fw2_batch *b, int32_t n);
+fw2_status fw2_batch_set_tile(fw2_batch *b, int32_t cols, int32_t rows);
+void fw2_batch_destroy(fw2_batch *b);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char *fw2_last_error(void);
 

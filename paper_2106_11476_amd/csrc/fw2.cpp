@@ -639,6 +639,197 @@ fw2_status fw2_check_finite(fw2_domain *d, float limit)
     return FW2_OK;
 }
 
+}  // extern "C"
+
+struct fw2_batch {
+    int max_domains = 0;
+    fw2::BatchTable *dev = nullptr;
+    fw2::BatchTable host;
+    std::vector<fw2_domain *> doms;
+    std::vector<int64_t> target;
+    hipStream_t stream = nullptr;
+    hipStream_t capture = nullptr;
+    hipGraphExec_t graph = nullptr;
+    int graph_chunk = 32;
+    int grid_blocks = 2048;
+    int rows = 4;
+    int bx = 256;
+};
+
+namespace {
+
+void batch_drop_graph(fw2_batch *b)
+{
+    if (b->graph) {
+        (void)hipGraphExecDestroy(b->graph);
+        b->graph = nullptr;
+    }
+}
+
+fw2_status batch_build_graph(fw2_batch *b)
+{
+    if (!b->capture) FW2_HIP(hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking));
+    FW2_HIP(hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < b->graph_chunk && e == hipSuccess; ++k)
+        e = fw2::launch_batch_step(b->dev, b->max_domains, b->grid_blocks, b->bx, b->capture);
+    hipGraph_t graph = nullptr;
+    hipError_t e2 = hipStreamEndCapture(b->capture, &graph);
+    if (e != hipSuccess || e2 != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return fail(FW2_E_HIP, std::string("batch capture: ") + hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    e = hipGraphInstantiate(&b->graph, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+        b->graph = nullptr;
+        return fail(FW2_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    }
+    return FW2_OK;
+}
+
+// Give domains that leave the batch their exact step counter back.
+fw2_status batch_release(fw2_batch *b)
+{
+    for (fw2_domain *d : b->doms) {
+        FW2_HIP(fw2::launch_set_counter(d->counter, d->step, b->stream));
+    }
+    FW2_HIP(hipStreamSynchronize(b->stream));
+    b->doms.clear();
+    b->target.clear();
+    return FW2_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+fw2_status fw2_batch_workspace_bytes(int32_t max_domains, uint64_t *bytes)
+{
+    if (max_domains < 1 || max_domains > fw2::kMaxBatch) return fail(FW2_E_INVALID, "max_domains must be in 1..64");
+    if (!bytes) return fail(FW2_E_INVALID, "bytes is NULL");
+    *bytes = align_up(sizeof(fw2::BatchTable), kAlign);
+    return FW2_OK;
+}
+
+fw2_status fw2_batch_create(int32_t max_domains, void *dev_workspace, uint64_t workspace_bytes, void *stream,
+                            fw2_batch **out)
+{
+    uint64_t need = 0;
+    fw2_status st = fw2_batch_workspace_bytes(max_domains, &need);
+    if (st != FW2_OK) return st;
+    if (!out) return fail(FW2_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!dev_workspace || (uintptr_t)dev_workspace % kAlign) return fail(FW2_E_INVALID, "workspace NULL or unaligned");
+    if (workspace_bytes < need) return fail(FW2_E_NOMEM, "batch workspace too small");
+    fw2_batch *b = new (std::nothrow) fw2_batch();
+    if (!b) return fail(FW2_E_NOMEM, "host allocation failed");
+    b->max_domains = max_domains;
+    b->dev = (fw2::BatchTable *)dev_workspace;
+    b->stream = (hipStream_t)stream;
+    std::memset(&b->host, 0, sizeof(b->host));
+    b->host.rows = b->rows;
+    hipError_t e = hipMemcpy(b->dev, &b->host, sizeof(b->host), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        delete b;
+        return fail(FW2_E_HIP, std::string("hipMemcpy: ") + hipGetErrorString(e));
+    }
+    *out = b;
+    return FW2_OK;
+}
+
+fw2_status fw2_batch_set_domains(fw2_batch *b, int32_t n, fw2_domain *const *domains, const int64_t *n_steps)
+{
+    if (!b) return fail(FW2_E_STATE, "batch is NULL");
+    if (n < 0 || n > b->max_domains) return fail(FW2_E_INVALID, "n out of range");
+    if (n > 0 && (!domains || !n_steps)) return fail(FW2_E_INVALID, "NULL domains or n_steps");
+    for (int32_t k = 0; k < n; ++k) {
+        const fw2_domain *d = domains[k];
+        if (!d) return fail(FW2_E_INVALID, "NULL domain");
+        if (d->desc.ndim != 2) return fail(FW2_E_UNSUPPORTED, "batched stepping is 2D only");
+        if (d->step >= n_steps[k]) return fail(FW2_E_INVALID, "domain already at or past its n_steps");
+        for (int32_t q = 0; q < k; ++q)
+            if (domains[q] == d) return fail(FW2_E_INVALID, "domain listed twice");
+    }
+    FW2_HIP(hipStreamSynchronize(b->stream));
+    fw2_status st = batch_release(b);
+    if (st != FW2_OK) return st;
+    fw2::BatchTable &T = b->host;
+    std::memset(&T, 0, sizeof(T));
+    T.rows = b->rows;
+    int tiles = 0, srcs = 0;
+    for (int32_t k = 0; k < n; ++k) {
+        fw2_domain *d = domains[k];
+        // the domain's own queued work must be finished before the batch stream touches it
+        FW2_HIP(hipStreamSynchronize(d->stream));
+        fw2::BatchEntry &e = T.e[k];
+        e.a = d->args;
+        e.src = d->src;
+        e.rcv = d->rcv;
+        e.n_steps = n_steps[k];
+        e.L = d->desc.n_relax;
+        e.scheme = d->desc.relax_scheme;
+        const int nbx = (d->ly.geo.n[0] + b->bx - 1) / b->bx;
+        const int nby = (d->ly.geo.n[1] + b->rows - 1) / b->rows;
+        e.tiles = nbx * nby;
+        e.tile_base = tiles;
+        e.src_base = srcs;
+        tiles += e.tiles;
+        srcs += d->src.n;
+        b->doms.push_back(d);
+        b->target.push_back(n_steps[k]);
+    }
+    T.n = n;
+    T.total_tiles = tiles;
+    T.total_src = srcs;
+    FW2_HIP(hipMemcpyAsync(b->dev, &T, sizeof(T), hipMemcpyHostToDevice, b->stream));
+    FW2_HIP(hipStreamSynchronize(b->stream));
+    return FW2_OK;
+}
+
+fw2_status fw2_batch_step(fw2_batch *b, int32_t n)
+{
+    if (!b) return fail(FW2_E_STATE, "batch is NULL");
+    if (n < 0) return fail(FW2_E_INVALID, "n < 0");
+    if (n == 0 || b->doms.empty()) return FW2_OK;
+    int32_t left = n;
+    if (b->graph_chunk > 0 && n >= b->graph_chunk) {
+        if (!b->graph) {
+            fw2_status st = batch_build_graph(b);
+            if (st != FW2_OK) return st;
+        }
+        for (; left >= b->graph_chunk; left -= b->graph_chunk) FW2_HIP(hipGraphLaunch(b->graph, b->stream));
+    }
+    for (; left > 0; --left) FW2_HIP(fw2::launch_batch_step(b->dev, b->max_domains, b->grid_blocks, b->bx, b->stream));
+    for (size_t k = 0; k < b->doms.size(); ++k)
+        b->doms[k]->step = std::min<int64_t>(b->doms[k]->step + n, b->target[k]);
+    return FW2_OK;
+}
+
+fw2_status fw2_batch_set_tile(fw2_batch *b, int32_t cols, int32_t rows)
+{
+    if (!b) return fail(FW2_E_STATE, "batch is NULL");
+    if (rows < 1 || rows > 1024) return fail(FW2_E_INVALID, "rows must be in 1..1024");
+    if (cols != 64 && cols != 256) return fail(FW2_E_INVALID, "cols must be 64 or 256");
+    if (!b->doms.empty()) return fail(FW2_E_STATE, "set the tile while the batch is empty");
+    if (cols != b->bx) batch_drop_graph(b);
+    b->bx = cols;
+    b->rows = rows;
+    b->host.rows = rows;
+    FW2_HIP(hipMemcpy(b->dev, &b->host, sizeof(b->host), hipMemcpyHostToDevice));
+    return FW2_OK;
+}
+
+void fw2_batch_destroy(fw2_batch *b)
+{
+    if (!b) return;
+    (void)hipStreamSynchronize(b->stream);
+    (void)batch_release(b);
+    batch_drop_graph(b);
+    if (b->capture) (void)hipStreamDestroy(b->capture);
+    delete b;
+}
+
 void fw2_destroy_domain(fw2_domain *d)
 {
     if (!d) return;

@@ -236,12 +236,13 @@ __device__ __forceinline__ void p_load_row(PRow<L> &r, const StepArgs &a, int i,
     }
 }
 
+// One tile (columns x0..x0+BX-1, rows y0..y0+rows-1) of the 2D pressure
+// sweep; sx / sy are the block's LDS rings.
 template <int L, bool CENTRED, int BX, bool PF>
-__global__ void __launch_bounds__(BX) pressure_sweep2d(const StepArgs a, int rows, int nbx, int nblocks)
+__device__ __forceinline__ void pressure_tile2d(const StepArgs &a, int rows, int x0, int y0,
+                                                float (*sx)[BX + 8], float (*sy)[BX + 2])
 {
     const Geometry &g = a.geo;
-    const int tile = tile_of_block(blockIdx.x, nblocks);
-    const int x0 = (tile % nbx) * BX, y0 = (tile / nbx) * rows;
     const int t = threadIdx.x;
     const int i = x0 + t;
     const int nx = g.n[0], ny = g.n[1];
@@ -250,9 +251,6 @@ __global__ void __launch_bounds__(BX) pressure_sweep2d(const StepArgs a, int row
     const float *__restrict__ vy = a.v + g.stride;
     float *__restrict__ pp = a.p;
     float *__restrict__ psi = a.psi2;
-
-    __shared__ float sx[4][BX + 8];     // v_x rows, column c <-> x0 - 4 + c
-    __shared__ float sy[3][BX + 2];     // v_y rows, column c <-> x0 - 1 + c
 
     // prologue: window rows y0-4 .. y0+2, rings rows y0-1 and y0
     float w[8];
@@ -354,12 +352,12 @@ __device__ __forceinline__ void v_load_row(VRow<L> &r, const StepArgs &a, int i,
     }
 }
 
+// One tile of the 2D velocity sweep; sp / sr / sk are the block's LDS rings.
 template <int L, bool CENTRED, int BX, bool PF>
-__global__ void __launch_bounds__(BX) velocity_sweep2d(const StepArgs a, int rows, int nbx, int nblocks)
+__device__ __forceinline__ void velocity_tile2d(const StepArgs &a, int rows, int x0, int y0,
+                                                float (*sp)[BX + 8], float (*sr)[BX + 1], float (*sk)[BX + 1])
 {
     const Geometry &g = a.geo;
-    const int tile = tile_of_block(blockIdx.x, nblocks);
-    const int x0 = (tile % nbx) * BX, y0 = (tile / nbx) * rows;
     const int t = threadIdx.x;
     const int i = x0 + t;
     const int nx = g.n[0], ny = g.n[1];
@@ -368,10 +366,6 @@ __global__ void __launch_bounds__(BX) velocity_sweep2d(const StepArgs a, int row
     float *__restrict__ vx = a.v;
     float *__restrict__ vy = a.v + g.stride;
     float *__restrict__ psi = a.psi1;
-
-    __shared__ float sp[4][BX + 8];     // p rows, column c <-> x0 - 4 + c
-    __shared__ float sr[3][BX + 1];     // rho rows, column c <-> x0 + c
-    __shared__ float sk[3][BX + 1];     // kappa0 rows
 
     // prologue: window rows y0-3 .. y0+3; p ring rows y0-1, y0; rho/kappa row y0
     float w[8];
@@ -465,6 +459,25 @@ __global__ void __launch_bounds__(BX) velocity_sweep2d(const StepArgs a, int row
         }
         if (PF) cur = nxt;
     }
+}
+
+template <int L, bool CENTRED, int BX, bool PF>
+__global__ void __launch_bounds__(BX) pressure_sweep2d(const StepArgs a, int rows, int nbx, int nblocks)
+{
+    __shared__ float sx[4][BX + 8];     // v_x rows, column c <-> x0 - 4 + c
+    __shared__ float sy[3][BX + 2];     // v_y rows, column c <-> x0 - 1 + c
+    const int tile = tile_of_block(blockIdx.x, nblocks);
+    pressure_tile2d<L, CENTRED, BX, PF>(a, rows, (tile % nbx) * BX, (tile / nbx) * rows, sx, sy);
+}
+
+template <int L, bool CENTRED, int BX, bool PF>
+__global__ void __launch_bounds__(BX) velocity_sweep2d(const StepArgs a, int rows, int nbx, int nblocks)
+{
+    __shared__ float sp[4][BX + 8];     // p rows, column c <-> x0 - 4 + c
+    __shared__ float sr[3][BX + 1];     // rho rows, column c <-> x0 + c
+    __shared__ float sk[3][BX + 1];     // kappa0 rows
+    const int tile = tile_of_block(blockIdx.x, nblocks);
+    velocity_tile2d<L, CENTRED, BX, PF>(a, rows, (tile % nbx) * BX, (tile / nbx) * rows, sp, sr, sk);
 }
 
 // ---------------------------------------------------------------------------
@@ -818,6 +831,108 @@ hipError_t launch_sweep3(const StepArgs &a, bool pressure, const KernelConfig &k
     return hipErrorInvalidValue;
 }
 
+// ---------------------------------------------------------------------------
+// Batched 2D step: the same per-tile code as the single-domain sweeps, over
+// the tiles of every entry of a device table.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int batch_entry_of_tile(const BatchTable *__restrict__ T, int t)
+{
+    int d = 0;
+    for (int k = 1; k < T->n; ++k)
+        if (T->e[k].tile_base <= t) d = k;
+    return d;
+}
+
+template <bool PRESSURE, int BX>
+__global__ void __launch_bounds__(BX) batch_phase(const BatchTable *__restrict__ T)
+{
+    __shared__ float r0[4][BX + 8];
+    __shared__ float r1[3][BX + 2];
+    __shared__ float r2[3][BX + 1];
+    __shared__ StepArgs sa;
+    const int total = T->total_tiles, rows = T->rows;
+    for (int t = blockIdx.x; t < total; t += gridDim.x) {
+        const int d = batch_entry_of_tile(T, t);
+        const BatchEntry &e = T->e[d];
+        const long long step = *e.rcv.step;
+        // pressure phase of step s runs while the counter reads s; velocity after it moved to s + 1
+        const bool active = PRESSURE ? step < e.n_steps : (step >= 1 && step <= e.n_steps);
+        if (!active) continue;                      // uniform over the block
+        {
+            const int *src = reinterpret_cast<const int *>(&e.a);
+            int *dst = reinterpret_cast<int *>(&sa);
+            for (int w = threadIdx.x; w < (int)(sizeof(StepArgs) / 4); w += BX) dst[w] = src[w];
+        }
+        __syncthreads();
+        const int nbx = (sa.geo.n[0] + BX - 1) / BX;
+        const int lt = t - e.tile_base;
+        const int x0 = (lt % nbx) * BX, y0 = (lt / nbx) * rows;
+        const int key = e.L * 2 + e.scheme;
+        if (PRESSURE) {
+            float(*sx)[BX + 8] = r0;
+            float(*sy)[BX + 2] = r1;
+            switch (key) {
+            case 2: pressure_tile2d<1, false, BX, false>(sa, rows, x0, y0, sx, sy); break;
+            case 3: pressure_tile2d<1, true, BX, false>(sa, rows, x0, y0, sx, sy); break;
+            case 4: pressure_tile2d<2, false, BX, false>(sa, rows, x0, y0, sx, sy); break;
+            case 5: pressure_tile2d<2, true, BX, false>(sa, rows, x0, y0, sx, sy); break;
+            case 6: pressure_tile2d<3, false, BX, false>(sa, rows, x0, y0, sx, sy); break;
+            case 7: pressure_tile2d<3, true, BX, false>(sa, rows, x0, y0, sx, sy); break;
+            case 8: pressure_tile2d<4, false, BX, false>(sa, rows, x0, y0, sx, sy); break;
+            case 9: pressure_tile2d<4, true, BX, false>(sa, rows, x0, y0, sx, sy); break;
+            default: break;
+            }
+        } else {
+            float(*sp)[BX + 8] = r0;
+            float(*sr)[BX + 1] = r2;
+            float(*sk)[BX + 1] = reinterpret_cast<float(*)[BX + 1]>(&r1[0][0]);
+            switch (key) {
+            case 2: velocity_tile2d<1, false, BX, false>(sa, rows, x0, y0, sp, sr, sk); break;
+            case 3: velocity_tile2d<1, true, BX, false>(sa, rows, x0, y0, sp, sr, sk); break;
+            case 4: velocity_tile2d<2, false, BX, false>(sa, rows, x0, y0, sp, sr, sk); break;
+            case 5: velocity_tile2d<2, true, BX, false>(sa, rows, x0, y0, sp, sr, sk); break;
+            case 6: velocity_tile2d<3, false, BX, false>(sa, rows, x0, y0, sp, sr, sk); break;
+            case 7: velocity_tile2d<3, true, BX, false>(sa, rows, x0, y0, sp, sr, sk); break;
+            case 8: velocity_tile2d<4, false, BX, false>(sa, rows, x0, y0, sp, sr, sk); break;
+            case 9: velocity_tile2d<4, true, BX, false>(sa, rows, x0, y0, sp, sr, sk); break;
+            default: break;
+            }
+        }
+        __syncthreads();                            // LDS rings and sa are reused by the next tile
+    }
+}
+
+__global__ void batch_sources(const BatchTable *__restrict__ T)
+{
+    const int total = T->total_src;
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < total; q += gridDim.x * blockDim.x) {
+        int d = 0;
+        for (int k = 1; k < T->n; ++k)
+            if (T->e[k].src_base <= q) d = k;
+        const BatchEntry &e = T->e[d];
+        const long long step = *e.src.step;
+        if (step >= e.n_steps || step >= e.src.n_t) continue;
+        const int lq = q - e.src_base;
+        const int64_t pi = padded_index(e.src.geo, e.src.idx[lq]);
+        e.src.p[pi] = e.src.p[pi] + e.src.w[lq] * e.src.signals[(int64_t)e.src.sig[lq] * e.src.n_t + step];
+    }
+}
+
+// One block per entry: record its receivers, then advance its counter.
+__global__ void __launch_bounds__(256) batch_receivers(const BatchTable *__restrict__ T)
+{
+    const int d = blockIdx.x;
+    if (d >= T->n) return;
+    const BatchEntry &e = T->e[d];
+    const long long step = *e.rcv.step;
+    if (step < e.n_steps && step < e.rcv.cap)
+        for (int r = threadIdx.x; r < e.rcv.n; r += blockDim.x)
+            e.rcv.trace[step * e.rcv.n + r] = e.rcv.p[padded_index(e.rcv.geo, e.rcv.idx[r])];
+    __syncthreads();
+    if (threadIdx.x == 0) e.rcv.step[0] = step + 1;
+}
+
 template <int NDIM, int L, bool C>
 hipError_t launch_p(const StepArgs &a, hipStream_t st)
 {
@@ -886,6 +1001,23 @@ hipError_t launch_sources(const SparseArgs &s, hipStream_t st)
 hipError_t launch_receivers(const SparseArgs &s, hipStream_t st)
 {
     hipLaunchKernelGGL(receiver_kernel, dim3(1), dim3(256), 0, st, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_step(const BatchTable *T, int n_entries_max, int grid_blocks, int bx, hipStream_t st)
+{
+    if (bx == 64) {
+        hipLaunchKernelGGL((batch_phase<true, 64>), dim3(grid_blocks * 4), dim3(64), 0, st, T);
+    } else {
+        hipLaunchKernelGGL((batch_phase<true, 256>), dim3(grid_blocks), dim3(256), 0, st, T);
+    }
+    hipLaunchKernelGGL(batch_sources, dim3(256), dim3(256), 0, st, T);
+    hipLaunchKernelGGL(batch_receivers, dim3(n_entries_max), dim3(256), 0, st, T);
+    if (bx == 64) {
+        hipLaunchKernelGGL((batch_phase<false, 64>), dim3(grid_blocks * 4), dim3(64), 0, st, T);
+    } else {
+        hipLaunchKernelGGL((batch_phase<false, 256>), dim3(grid_blocks), dim3(256), 0, st, T);
+    }
     return hipGetLastError();
 }
 

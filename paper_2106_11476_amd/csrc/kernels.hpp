@@ -73,6 +73,33 @@ struct KernelConfig {
     int rows;
 };
 
+// Many 2D domains advanced by one launch per phase (batched serving).  The
+// table lives in device memory; blocks of a fixed, persistent grid walk all
+// tiles of all entries, so a captured step loop does not depend on which
+// domains are active.  A domain whose step counter has reached n_steps is
+// skipped (its counter keeps counting while it stays in the table).
+constexpr int kMaxBatch = 64;
+
+struct BatchEntry {
+    StepArgs a;
+    SparseArgs src, rcv;
+    long long n_steps;
+    int32_t L, scheme;
+    int32_t tile_base, tiles;        // tiles of bx columns x rows
+    int32_t src_base;                // first index in the flattened source list
+};
+
+struct BatchTable {
+    int32_t n;
+    int32_t total_tiles;
+    int32_t total_src;
+    int32_t rows;                    // tile rows; tile columns bx = 64 or 256
+    BatchEntry e[kMaxBatch];
+};
+
+hipError_t launch_batch_step(const BatchTable *dev_table, int n_entries_max, int grid_blocks, int bx,
+                             hipStream_t stream);
+
 // Launchers (kernels.hip).  All enqueue on `stream` and return the launch error.
 hipError_t launch_pressure(const StepArgs &a, int L, int scheme, const KernelConfig &kc, hipStream_t stream);
 hipError_t launch_velocity(const StepArgs &a, int L, int scheme, const KernelConfig &kc, hipStream_t stream);

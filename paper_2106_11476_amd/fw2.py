@@ -22,7 +22,9 @@ RELAX_PRINTED, RELAX_CENTRED = 0, 1
 EXPORTS = ["fw2_workspace_bytes", "fw2_create_domain", "fw2_add_source", "fw2_add_receivers",
            "fw2_step", "fw2_read_fields", "fw2_write_fields", "fw2_current_step",
            "fw2_set_current_step", "fw2_set_graph_chunk", "fw2_enable_kernel_timing",
-           "fw2_get_kernel_timing", "fw2_check_finite", "fw2_last_error", "fw2_destroy_domain"]
+           "fw2_get_kernel_timing", "fw2_check_finite", "fw2_last_error", "fw2_destroy_domain",
+           "fw2_batch_workspace_bytes", "fw2_batch_create", "fw2_batch_set_domains",
+           "fw2_batch_step", "fw2_batch_set_tile", "fw2_batch_destroy"]
 
 
 class Fw2Error(RuntimeError):
@@ -68,6 +70,11 @@ def lib():
             "fw2_enable_kernel_timing": [vp, i32],
             "fw2_get_kernel_timing": [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)],
             "fw2_check_finite": [vp, ctypes.c_float],
+            "fw2_batch_workspace_bytes": [i32, ctypes.POINTER(u64)],
+            "fw2_batch_create": [i32, vp, u64, vp, ctypes.POINTER(vp)],
+            "fw2_batch_set_domains": [vp, i32, ctypes.POINTER(vp), ctypes.POINTER(i64)],
+            "fw2_batch_step": [vp, i32],
+            "fw2_batch_set_tile": [vp, i32, i32],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -79,6 +86,8 @@ def lib():
         L.fw2_last_error.restype = ctypes.c_char_p
         L.fw2_destroy_domain.argtypes = [vp]
         L.fw2_destroy_domain.restype = None
+        L.fw2_batch_destroy.argtypes = [vp]
+        L.fw2_batch_destroy.restype = None
         _lib = L
     return _lib
 
@@ -267,6 +276,50 @@ class Domain:
     def __del__(self):
         try:
             self.destroy_domain()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Batched stepping of several resident 2D domains (fw2_batch_*)."""
+
+    def __init__(self, max_domains=64, device="cuda", stream=None):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
+        nb = ctypes.c_uint64(0)
+        _check(lib().fw2_batch_workspace_bytes(int(max_domains), ctypes.byref(nb)))
+        self.workspace = torch.empty(int(nb.value), dtype=torch.uint8, device=self.device)
+        torch.cuda.synchronize(self.device)
+        h = ctypes.c_void_p()
+        _check(lib().fw2_batch_create(int(max_domains), ctypes.c_void_p(self.workspace.data_ptr()),
+                                      int(nb.value), ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
+        self._h = h
+        self.max_domains = int(max_domains)
+        self.domains = []
+
+    def set_domains(self, domains, n_steps):
+        n = len(domains)
+        arr = (ctypes.c_void_p * max(n, 1))(*[d._h.value for d in domains])
+        steps = (ctypes.c_int64 * max(n, 1))(*[int(x) for x in n_steps])
+        _check(lib().fw2_batch_set_domains(self._h, n, arr, steps))
+        self.domains = list(domains)
+
+    def step(self, n):
+        _check(lib().fw2_batch_step(self._h, int(n)))
+
+    def set_tile(self, cols, rows):
+        _check(lib().fw2_batch_set_tile(self._h, int(cols), int(rows)))
+
+    def destroy(self):
+        if getattr(self, "_h", None):
+            lib().fw2_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
         except Exception:
             pass
 

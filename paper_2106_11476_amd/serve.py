@@ -1,0 +1,212 @@
+"""Continuous-batching request loop over libfw2's batched stepping.
+
+Requests (2D simulations of any size, mechanism count and step count) arrive
+over time.  The server keeps every admitted simulation resident in HBM and
+advances all of them together with fw2_batch_step, one launch per phase over
+the tiles of every active domain.  At each chunk boundary finished requests
+hand back their receiver traces and free their memory, and queued requests
+are admitted in arrival order while the device-memory budget and the slot
+count allow.  Work of different requests therefore overlaps on the device,
+and a request's results do not depend on what it was batched with.
+
+The plain baseline runs the same requests one at a time in arrival order
+with the single-domain path of the same library.
+"""
+import time
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import numpy as np
+
+from . import fw2
+
+
+@dataclass
+class Request:
+    rid: int
+    problem: object              # workloads.Problem-like inputs (2D)
+    n_steps: int
+    arrival: float = 0.0         # seconds after the stream starts
+    admitted: Optional[float] = None
+    done: Optional[float] = None
+    trace: Optional[np.ndarray] = None
+    footprint: int = 0
+
+
+def footprint_bytes(prob, n_steps):
+    """Device bytes a request holds while resident: workspace, trace buffer,
+    source tables."""
+    ws = fw2.workspace_bytes(prob)
+    n_rcv = max(len(prob.rcv_idx), 1)
+    src = len(prob.src_idx) * (8 + 4 + 4) + np.asarray(prob.signals).size * 4
+    return int(ws + n_steps * n_rcv * 4 + src + 8 * n_rcv)
+
+
+def admit(queue, active_bytes, budget, free_slots, now):
+    """Arrival-order admission: take queued requests that have arrived while
+    the memory budget and the free slots allow; a request that does not fit
+    blocks the ones behind it (no overtaking, so no starvation)."""
+    chosen = []
+    used = active_bytes
+    for r in queue:
+        if r.arrival > now or len(chosen) >= free_slots:
+            break
+        if used + r.footprint > budget:
+            break
+        chosen.append(r)
+        used += r.footprint
+    return chosen
+
+
+@dataclass
+class Stats:
+    completed: int = 0
+    makespan: float = 0.0
+    latencies: List[float] = field(default_factory=list)
+    peak_bytes: int = 0
+    peak_active: int = 0
+
+    def summary(self):
+        lat = np.asarray(self.latencies) if self.latencies else np.zeros(1)
+        return {"completed": self.completed, "makespan_s": round(self.makespan, 4),
+                "sims_per_s": round(self.completed / self.makespan, 4) if self.makespan > 0 else None,
+                "p50_latency_s": round(float(np.percentile(lat, 50)), 4),
+                "p99_latency_s": round(float(np.percentile(lat, 99)), 4),
+                "peak_resident_bytes": int(self.peak_bytes), "peak_active": int(self.peak_active)}
+
+
+class Server:
+    """Continuous batching on one GPU.
+
+    budget_bytes -- device memory the resident requests may hold together
+    max_active   -- largest number of requests advanced by one launch (<= 64)
+    chunk        -- steps between admission / completion points
+    """
+
+    def __init__(self, budget_bytes, max_active=32, chunk=64, device="cuda:0", tile=(256, 4)):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.budget = int(budget_bytes)
+        self.max_active = int(max_active)
+        self.chunk = int(chunk)
+        self.stream = torch.cuda.Stream(device=self.device)
+        self.batch = fw2.Batch(max_domains=self.max_active, device=self.device, stream=self.stream)
+        self.batch.set_tile(*tile)
+
+    def _start(self, r):
+        dom = fw2.Domain(r.problem, device=self.device, stream=self.stream)
+        if len(r.problem.src_idx):
+            dom.add_source(r.problem.src_idx, r.problem.src_sig, r.problem.src_w, r.problem.signals)
+        dom.add_receivers(r.problem.rcv_idx, r.n_steps)
+        return dom
+
+    def run(self, requests, clock=time.perf_counter):
+        """Serve the requests (sorted by arrival); returns Stats."""
+        queue = sorted(requests, key=lambda r: (r.arrival, r.rid))
+        for r in queue:
+            r.footprint = footprint_bytes(r.problem, r.n_steps)
+            if r.footprint > self.budget:
+                raise ValueError("request %d needs %d bytes, above the budget" % (r.rid, r.footprint))
+        active = []               # (request, domain)
+        stats = Stats()
+        t0 = clock()
+        while queue or active:
+            now = clock() - t0
+            used = sum(r.footprint for r, _ in active)
+            new = admit(queue, used, self.budget, self.max_active - len(active), now)
+            for r in new:
+                queue.remove(r)
+                r.admitted = clock() - t0
+                active.append((r, self._start(r)))
+            if new:
+                self.batch.set_domains([d for _, d in active], [r.n_steps for r, _ in active])
+            if not active:
+                wait = queue[0].arrival - (clock() - t0)
+                if wait > 0:
+                    time.sleep(min(wait, 0.05))
+                continue
+            stats.peak_bytes = max(stats.peak_bytes, sum(r.footprint for r, _ in active))
+            stats.peak_active = max(stats.peak_active, len(active))
+            # run until the next event: the first completion, or (when a slot is
+            # free and a request is queued) the next chunk boundary
+            to_done = min(r.n_steps - d.current_step() for r, d in active)
+            k = to_done if (not queue or len(active) >= self.max_active) else min(to_done, self.chunk)
+            self.batch.step(max(int(k), 1))
+            self.stream.synchronize()
+            finished = [(r, d) for r, d in active if d.current_step() >= r.n_steps]
+            if finished:
+                keep = [(r, d) for r, d in active if d.current_step() < r.n_steps]
+                self.batch.set_domains([d for _, d in keep], [r.n_steps for r, _ in keep])
+                for r, d in finished:
+                    r.trace = d.trace.cpu().numpy()
+                    r.done = clock() - t0
+                    stats.latencies.append(r.done - r.arrival)
+                    stats.completed += 1
+                    d.destroy_domain()
+                active = keep
+        stats.makespan = clock() - t0
+        return stats
+
+    def close(self):
+        self.batch.destroy()
+
+
+def run_plain(requests, device="cuda:0", clock=time.perf_counter):
+    """The same requests one at a time in arrival order (single-domain path)."""
+    import torch
+    dev = torch.device(device)
+    stream = torch.cuda.Stream(device=dev)
+    stats = Stats()
+    t0 = clock()
+    for r in sorted(requests, key=lambda q: (q.arrival, q.rid)):
+        wait = r.arrival - (clock() - t0)
+        if wait > 0:
+            time.sleep(wait)
+        r.admitted = clock() - t0
+        dom = fw2.Domain(r.problem, device=dev, stream=stream)
+        if len(r.problem.src_idx):
+            dom.add_source(r.problem.src_idx, r.problem.src_sig, r.problem.src_w, r.problem.signals)
+        dom.add_receivers(r.problem.rcv_idx, r.n_steps)
+        dom.step(r.n_steps)
+        stream.synchronize()
+        r.trace = dom.trace.cpu().numpy()
+        dom.destroy_domain()
+        r.done = clock() - t0
+        stats.latencies.append(r.done - r.arrival)
+        stats.completed += 1
+        stats.peak_active = 1
+    stats.makespan = clock() - t0
+    return stats
+
+
+def autotune_tile(problems, candidates=((256, 2), (256, 4), (256, 8), (64, 4), (64, 8), (64, 16)),
+                  steps=32, device="cuda:0"):
+    """Pick the batched sweep's tile (columns, rows) by timing each candidate
+    on a batch of zero-state copies of the given problems (sources are not
+    attached, so the fields stay zero and nothing is consumed)."""
+    import torch
+    dev = torch.device(device)
+    stream = torch.cuda.Stream(device=dev)
+    doms = [fw2.Domain(p, device=dev, stream=stream) for p in problems]
+    best, timings = None, {}
+    batch = fw2.Batch(max_domains=max(len(doms), 1), device=dev, stream=stream)
+    for rows in candidates:
+        batch.set_domains([], [])
+        batch.set_tile(*rows)
+        batch.set_domains(doms, [10 ** 9] * len(doms))
+        batch.step(steps)                          # warm-up (also builds the graph)
+        stream.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        batch.step(steps)
+        e1.record(stream)
+        stream.synchronize()
+        timings[rows] = e0.elapsed_time(e1) / steps
+        if best is None or timings[rows] < timings[best]:
+            best = rows
+    batch.set_domains([], [])
+    batch.destroy()
+    for d in doms:
+        d.destroy_domain()
+    return best, timings

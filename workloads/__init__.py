@@ -367,3 +367,38 @@ def skull_3d(n=1024, nb=48, ntr=36, seed=3, n_steps=4000, ppw=12, f0=1e6, cfl=0.
     ci = int(round(ctr))
     prob.rcv_idx = prob.flat(np.full(zr.size, ci), np.full(zr.size, ci), zr)
     return prob
+
+
+# ---------------------------------------------------------------------------
+# Workload 4: stream of 2D requests for batched serving
+# ---------------------------------------------------------------------------
+
+def serving_requests(n=256, seed=4, sides=(1024, 3072), side_step=256, f0_range=(1e6, 5e6),
+                     L_choices=(2, 3, 4), steps_per_depth=2.5, rate=None, max_steps=None):
+    """Seeded stream of n square 2D requests.  Request i uses seed 4000 + i:
+    side drawn from {sides[0], sides[0] + side_step, ..., sides[1]}, f0 from
+    U[f0_range], L from L_choices, the layered abdominal recipe with
+    scatterers scaled by area, and n_steps = steps_per_depth * side (one depth
+    crossing at CFL 0.4), capped at max_steps.  With a rate, arrivals are a
+    Poisson process of that rate (requests per second); otherwise all arrive
+    at t = 0.  Returns a list of (problem, n_steps, arrival)."""
+    rng = np.random.default_rng(seed)
+    side_set = np.arange(sides[0], sides[1] + 1, side_step)
+    t = 0.0
+    out = []
+    for i in range(n):
+        r = np.random.default_rng(4000 + i)
+        side = int(side_set[r.integers(len(side_set))])
+        f0 = float(r.uniform(*f0_range))
+        L = int(L_choices[r.integers(len(L_choices))])
+        steps = int(round(steps_per_depth * side))
+        if max_steps:
+            steps = min(steps, int(max_steps))
+        n_sc = int(1e5 * side * side / (4096 * 2048))
+        prob = abdominal_2d(nx=side, ny=side, seed=4000 + i, n_steps=steps, f0=f0, L=L,
+                            n_scatter=max(n_sc, 1), n_elem=min(128, max(4, (side - 96) // 12)))
+        prob.name = "request_%d_%dx%d_L%d" % (i, side, side, L)
+        if rate:
+            t += rng.exponential(1.0 / rate)
+        out.append((prob, steps, t if rate else 0.0))
+    return out
