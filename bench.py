@@ -8,7 +8,9 @@ relaxation mechanisms, 9 tissue labels, 128-element array, 3 MHz).
 
 Prints one JSON line: Gpoint-updates/s over the timed steps, the roofline of
 the dominant kernel (HIP-event durations on the domain's stream, algorithmic
-bytes per launch) and the FP64 CPU oracle timed on a bounded sample.
+bytes per launch), batched-serving sims/s and p50/p99 latency against the
+plain one-at-a-time solver, and the FP64 CPU oracle timed on a bounded
+sample.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload abdominal_2d|plain_2d|skull_3d]
 """
@@ -123,6 +125,44 @@ def probe_copy(torch, dev, mib, reps=10):
     return {"bytes_per_copy": moved, "ms": round(ms, 4), "GBps": round(moved / ms / 1e6, 1), "reps": reps}
 
 
+def serving_leg(seed=4):
+    """Continuous batching vs the plain one-at-a-time solver on two seeded
+    request streams: the heterogeneous 2D recipe at 512^2-1024^2 (the served
+    workload's recipe, scaled so the leg takes seconds) and small 128^2-384^2
+    grids.  Capacity: all requests queued at t = 0.  Latency: Poisson
+    arrivals at 1.2x the plain solver's capacity."""
+    import workloads as W
+    from paper_2106_11476_amd import serve
+    out = {}
+    for name, (n, sides, step) in (("heterogeneous_512_1024", (48, (512, 1024), 128)),
+                                   ("small_128_384", (96, (128, 384), 64))):
+        raw = W.serving_requests(n=n, seed=seed, sides=sides, side_step=step)
+        upd = sum(p.npts * k for p, k, _ in raw)
+        mk = lambda arr: [serve.Request(i, p, k, a) for i, ((p, k, _), a) in enumerate(zip(raw, arr))]
+        tile, _ = serve.autotune_tile([p for p, _, _ in raw[:4]], steps=32)
+        med = float(np.median([serve.footprint_bytes(p, k) for p, k, _ in raw]))
+        budget = int(24 * med)
+        p0 = serve.run_plain(mk([0.0] * n))
+        srv = serve.Server(budget_bytes=budget, max_active=32, chunk=64, tile=tile)
+        b0 = srv.run(mk([0.0] * n))
+        lam = 1.2 * p0.completed / p0.makespan
+        arr = np.cumsum(np.random.default_rng(seed + 40).exponential(1.0 / lam, n))
+        pl = serve.run_plain(mk(arr))
+        bt = srv.run(mk(arr))
+        srv.close()
+        out[name] = {
+            "requests": n, "sides": list(sides), "tile": list(tile), "budget_bytes": budget,
+            "capacity_sims_per_s": {"plain": round(p0.completed / p0.makespan, 3),
+                                    "batched": round(b0.completed / b0.makespan, 3)},
+            "capacity_gpoint_updates_per_s": {"plain": round(upd / p0.makespan / 1e9, 3),
+                                              "batched": round(upd / b0.makespan / 1e9, 3)},
+            "capacity_speedup": round(p0.makespan / b0.makespan, 3),
+            "poisson_rate_per_s": round(lam, 3),
+            "poisson": {"plain": pl.summary(), "batched": bt.summary()},
+        }
+    return out
+
+
 def _db_rows(db, sql):
     import sqlite3
     con = sqlite3.connect(db)
@@ -197,6 +237,7 @@ def main():
     ap.add_argument("--workload", default="abdominal_2d")
     ap.add_argument("--n3d", type=int, default=1024, help="cube side of the skull_3d workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serving", action="store_true", help="skip the batched-serving leg")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first time a plain device copy of this size (bandwidth reference, "
                          "and the known-size kernel for scaling HBM counters)")
@@ -268,6 +309,8 @@ def main():
     if copy_probe is not None:
         out["copy_probe"] = copy_probe
     dom.destroy_domain()
+    if not args.no_serving and args.workload != "skull_3d":
+        out["serving"] = serving_leg()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob)
     print(json.dumps(out), flush=True)
