@@ -162,6 +162,35 @@ fw2_status fw2_get_kernel_timing(fw2_domain *dom, double ms[2], int64_t count[2]
  * below limit in magnitude; FW2_E_UNSTABLE otherwise. */
 fw2_status fw2_check_finite(fw2_domain *dom, float limit);
 
+/* ---- State blocks and the discrete adjoint ------------------------------
+ * The state of a domain (p, v, psi1, psi2 in the library's padded layout) is
+ * one contiguous block of fw2_state_bytes bytes.  fw2_save_state copies it to
+ * a caller-owned device buffer and fw2_load_state copies one back and sets
+ * the step counter (both asynchronous on the domain's stream): checkpoints.
+ *
+ * The discrete adjoint (the paper's extension to full waveform inversion:
+ * the relaxation is not time-reversible, so its adjoint is derived
+ * explicitly) gives the gradient of J = 1/2 sum_k sum_r (trace[k][r] -
+ * obs[k][r])^2 with respect to the sound-speed map.  It is the exact
+ * transpose of the time-centred scheme's step (FW2_RELAX_CENTRED only;
+ * FW2_E_UNSUPPORTED otherwise), linearised about the forward state; c enters
+ * through kappa0 = 1/(rho c^2) (fd_r and pml_cp are fixed inputs).
+ *   fw2_adjoint_begin: attaches a caller-owned device workspace of
+ *     fw2_adjoint_workspace_bytes (256-byte aligned) and zeroes the adjoint
+ *     state and the gradient.
+ *   fw2_adjoint_step: reverse of forward step `step`, given the saved state
+ *     block at that step's input and the device residual trace[step] - obs[step]
+ *     ([n_rcv] FP32, or NULL for no residual).  Call for step = n-1 down to 0.
+ *   fw2_adjoint_gradient: dJ/dc, packed FP32 [nz][ny][nx] into dst (host or
+ *     device); synchronises. */
+fw2_status fw2_state_bytes(const fw2_domain *dom, uint64_t *bytes);
+fw2_status fw2_save_state(fw2_domain *dom, void *dev_dst);
+fw2_status fw2_load_state(fw2_domain *dom, const void *dev_src, int64_t step);
+fw2_status fw2_adjoint_workspace_bytes(const fw2_domain *dom, uint64_t *bytes);
+fw2_status fw2_adjoint_begin(fw2_domain *dom, void *dev_workspace, uint64_t workspace_bytes);
+fw2_status fw2_adjoint_step(fw2_domain *dom, const void *dev_state, int64_t step, const float *dev_residual);
+fw2_status fw2_adjoint_gradient(fw2_domain *dom, float *dst, int32_t dst_kind);
+
 /* ---- Batched stepping of many 2D domains (continuous batching) ----------
  * A batch advances several resident 2D domains of any sizes, L and memory
  * scheme with one launch per phase: blocks of a fixed grid walk the tiles of

@@ -6,7 +6,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libfw2.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("fw2.cpp", "setup.cpp", "kernels.hip")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("fw2.cpp", "setup.cpp", "kernels.hip", "adjoint.hip")]
 FLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-shared",
          # no packed FP32 instructions in any device code
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

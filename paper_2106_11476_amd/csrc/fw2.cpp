@@ -159,6 +159,8 @@ struct fw2_domain {
     int64_t timed_steps = 0;
     double ms[2] = {0.0, 0.0};
     int64_t count[2] = {0, 0};
+    bool adjoint = false;
+    fw2::AdjointBuffers adj;
     int64_t npts() const { return (int64_t)ly.geo.n[0] * ly.geo.n[1] * ly.geo.n[2]; }
 };
 
@@ -623,6 +625,99 @@ fw2_status fw2_get_kernel_timing(fw2_domain *d, double ms[2], int64_t count[2])
     ms[1] = d->ms[1];
     count[0] = d->count[0];
     count[1] = d->count[1];
+    return FW2_OK;
+}
+
+static int64_t state_floats(const fw2_domain *d)
+{
+    const int nd = d->desc.ndim, L = d->desc.n_relax;
+    return (int64_t)(1 + nd + 2 * nd * L) * d->ly.geo.stride;
+}
+
+fw2_status fw2_state_bytes(const fw2_domain *d, uint64_t *bytes)
+{
+    if (!d) return fail(FW2_E_STATE, "domain is NULL");
+    if (!bytes) return fail(FW2_E_INVALID, "bytes is NULL");
+    *bytes = (uint64_t)state_floats(d) * 4;
+    return FW2_OK;
+}
+
+fw2_status fw2_save_state(fw2_domain *d, void *dev_dst)
+{
+    if (!d) return fail(FW2_E_STATE, "domain is NULL");
+    if (!dev_dst) return fail(FW2_E_INVALID, "dst is NULL");
+    FW2_HIP(hipMemcpyAsync(dev_dst, d->args.p, (size_t)state_floats(d) * 4, hipMemcpyDeviceToDevice, d->stream));
+    return FW2_OK;
+}
+
+fw2_status fw2_load_state(fw2_domain *d, const void *dev_src, int64_t step)
+{
+    if (!d) return fail(FW2_E_STATE, "domain is NULL");
+    if (!dev_src || step < 0) return fail(FW2_E_INVALID, "src is NULL or step < 0");
+    FW2_HIP(hipMemcpyAsync(d->args.p, dev_src, (size_t)state_floats(d) * 4, hipMemcpyDeviceToDevice, d->stream));
+    FW2_HIP(fw2::launch_set_counter(d->counter, step, d->stream));
+    d->step = step;
+    return FW2_OK;
+}
+
+fw2_status fw2_adjoint_workspace_bytes(const fw2_domain *d, uint64_t *bytes)
+{
+    if (!d) return fail(FW2_E_STATE, "domain is NULL");
+    if (!bytes) return fail(FW2_E_INVALID, "bytes is NULL");
+    const int nd = d->desc.ndim;
+    *bytes = (uint64_t)(state_floats(d) + (int64_t)(4 + 4 * nd) * d->ly.geo.stride) * 4;
+    return FW2_OK;
+}
+
+fw2_status fw2_adjoint_begin(fw2_domain *d, void *dev_workspace, uint64_t bytes)
+{
+    if (!d) return fail(FW2_E_STATE, "domain is NULL");
+    if (d->desc.relax_scheme != FW2_RELAX_CENTRED)
+        return fail(FW2_E_UNSUPPORTED, "the adjoint is derived for the time-centred memory scheme");
+    uint64_t need = 0;
+    fw2_status st = fw2_adjoint_workspace_bytes(d, &need);
+    if (st != FW2_OK) return st;
+    if (!dev_workspace || (uintptr_t)dev_workspace % kAlign) return fail(FW2_E_INVALID, "workspace NULL or unaligned");
+    if (bytes < need) return fail(FW2_E_NOMEM, "adjoint workspace too small");
+    const int64_t S = d->ly.geo.stride;
+    const int nd = d->desc.ndim;
+    float *base = (float *)dev_workspace;
+    fw2::AdjointBuffers &b = d->adj;
+    b.lp = base;
+    b.pp = base + state_floats(d);
+    b.sS = b.pp + S;
+    b.lDv = b.sS + S;
+    b.lpb = b.lDv + nd * S;
+    b.lkv = b.lpb + nd * S;
+    b.lDp = b.lkv + nd * S;
+    b.gk = b.lDp + nd * S;
+    b.out = b.gk + S;
+    FW2_HIP(hipMemsetAsync(dev_workspace, 0, need, d->stream));
+    d->adjoint = true;
+    return FW2_OK;
+}
+
+fw2_status fw2_adjoint_step(fw2_domain *d, const void *dev_state, int64_t step, const float *dev_residual)
+{
+    if (!d) return fail(FW2_E_STATE, "domain is NULL");
+    if (!d->adjoint) return fail(FW2_E_STATE, "fw2_adjoint_begin first");
+    if (!dev_state || step < 0) return fail(FW2_E_INVALID, "state is NULL or step < 0");
+    FW2_HIP(fw2::launch_adjoint_step(d->args, d->src, d->rcv, d->desc.n_relax, (const float *)dev_state, d->adj, step,
+                                     dev_residual, d->stream));
+    return FW2_OK;
+}
+
+fw2_status fw2_adjoint_gradient(fw2_domain *d, float *dst, int32_t kind)
+{
+    if (!d) return fail(FW2_E_STATE, "domain is NULL");
+    if (!d->adjoint) return fail(FW2_E_STATE, "fw2_adjoint_begin first");
+    if (!dst || (kind != FW2_HOST && kind != FW2_DEVICE)) return fail(FW2_E_INVALID, "bad destination");
+    FW2_HIP(fw2::launch_adjoint_gradient(d->args, d->adj, d->stream));
+    const hipMemcpyKind k = kind == FW2_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    const int ext[3] = {d->ly.geo.n[0], d->ly.geo.n[1], d->ly.geo.n[2]};
+    fw2_status st = copy_box(d, d->adj.out, dst, false, k, ext);
+    if (st != FW2_OK) return st;
+    FW2_HIP(hipStreamSynchronize(d->stream));
     return FW2_OK;
 }
 

@@ -100,6 +100,16 @@ struct BatchTable {
 hipError_t launch_batch_step(const BatchTable *dev_table, int n_entries_max, int grid_blocks, int bx,
                              hipStream_t stream);
 
+// Discrete adjoint of one step (adjoint.hip): device arrays of the adjoint
+// state (same layout as the forward state block) and the per-step temporaries.
+struct AdjointBuffers {
+    float *lp, *pp, *sS, *lDv, *lpb, *lkv, *lDp, *gk, *out;
+};
+hipError_t launch_adjoint_step(const StepArgs &f, const SparseArgs &src, const SparseArgs &rcv, int L,
+                               const float *state, const AdjointBuffers &b, long long step,
+                               const float *residual, hipStream_t stream);
+hipError_t launch_adjoint_gradient(const StepArgs &f, const AdjointBuffers &b, hipStream_t stream);
+
 // Launchers (kernels.hip).  All enqueue on `stream` and return the launch error.
 hipError_t launch_pressure(const StepArgs &a, int L, int scheme, const KernelConfig &kc, hipStream_t stream);
 hipError_t launch_velocity(const StepArgs &a, int L, int scheme, const KernelConfig &kc, hipStream_t stream);

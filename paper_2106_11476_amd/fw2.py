@@ -24,7 +24,9 @@ EXPORTS = ["fw2_workspace_bytes", "fw2_create_domain", "fw2_add_source", "fw2_ad
            "fw2_set_current_step", "fw2_set_graph_chunk", "fw2_enable_kernel_timing",
            "fw2_get_kernel_timing", "fw2_check_finite", "fw2_last_error", "fw2_destroy_domain",
            "fw2_batch_workspace_bytes", "fw2_batch_create", "fw2_batch_set_domains",
-           "fw2_batch_step", "fw2_batch_set_tile", "fw2_batch_destroy"]
+           "fw2_batch_step", "fw2_batch_set_tile", "fw2_batch_destroy",
+           "fw2_state_bytes", "fw2_save_state", "fw2_load_state", "fw2_adjoint_workspace_bytes",
+           "fw2_adjoint_begin", "fw2_adjoint_step", "fw2_adjoint_gradient"]
 
 
 class Fw2Error(RuntimeError):
@@ -75,6 +77,13 @@ def lib():
             "fw2_batch_set_domains": [vp, i32, ctypes.POINTER(vp), ctypes.POINTER(i64)],
             "fw2_batch_step": [vp, i32],
             "fw2_batch_set_tile": [vp, i32, i32],
+            "fw2_state_bytes": [vp, ctypes.POINTER(u64)],
+            "fw2_save_state": [vp, vp],
+            "fw2_load_state": [vp, vp, i64],
+            "fw2_adjoint_workspace_bytes": [vp, ctypes.POINTER(u64)],
+            "fw2_adjoint_begin": [vp, vp, u64],
+            "fw2_adjoint_step": [vp, vp, i64, vp],
+            "fw2_adjoint_gradient": [vp, vp, i32],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -223,6 +232,41 @@ class Domain:
 
     def check_finite(self, limit=1e12):
         _check(lib().fw2_check_finite(self._h, float(limit)))
+
+    # -- state blocks and the discrete adjoint -----------------------------
+    def state_bytes(self):
+        n = ctypes.c_uint64(0)
+        _check(lib().fw2_state_bytes(self._h, ctypes.byref(n)))
+        return int(n.value)
+
+    def new_state_buffer(self, count=None):
+        """Device buffer for one state block, or [count] blocks."""
+        shape = (self.state_bytes() // 4,) if count is None else (int(count), self.state_bytes() // 4)
+        return self.torch.empty(shape, dtype=self.torch.float32, device=self.device)
+
+    def save_state(self, dst):
+        _check(lib().fw2_save_state(self._h, ctypes.c_void_p(dst.data_ptr())))
+
+    def load_state(self, src, step):
+        _check(lib().fw2_load_state(self._h, ctypes.c_void_p(src.data_ptr()), int(step)))
+
+    def adjoint_begin(self):
+        n = ctypes.c_uint64(0)
+        _check(lib().fw2_adjoint_workspace_bytes(self._h, ctypes.byref(n)))
+        self._adj_ws = self.torch.empty(int(n.value), dtype=self.torch.uint8, device=self.device)
+        self.torch.cuda.synchronize(self.device)
+        _check(lib().fw2_adjoint_begin(self._h, ctypes.c_void_p(self._adj_ws.data_ptr()), int(n.value)))
+
+    def adjoint_step(self, state, step, residual=None):
+        r = ctypes.c_void_p(residual.data_ptr()) if residual is not None else None
+        _check(lib().fw2_adjoint_step(self._h, ctypes.c_void_p(state.data_ptr()), int(step), r))
+
+    def adjoint_gradient(self):
+        """dJ/dc as a device tensor of the grid's shape ([nz][ny][nx])."""
+        out = self.torch.empty(self.shape[::-1],
+                               dtype=self.torch.float32, device=self.device)
+        _check(lib().fw2_adjoint_gradient(self._h, ctypes.c_void_p(out.data_ptr()), DEVICE))
+        return out
 
     def _sizes(self, mask):
         grid = self.shape[::-1]
