@@ -9,7 +9,9 @@ relaxation mechanisms, 9 tissue labels, 128-element array, 3 MHz).
 Prints one JSON line: Gpoint-updates/s over the timed steps, the roofline of
 the dominant kernel (HIP-event durations on the domain's stream, algorithmic
 bytes per launch), batched-serving sims/s and p50/p99 latency against the
-plain one-at-a-time solver, and the FP64 CPU oracle timed on a bounded
+plain one-at-a-time solver, the sound-speed gradient of one shot of the
+1536^2 inversion workload (checkpointed forward + reverse steps, with the
+reverse step's own roofline), and the FP64 CPU oracle timed on a bounded
 sample.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload abdominal_2d|plain_2d|skull_3d]
@@ -163,6 +165,75 @@ def serving_leg(seed=4):
     return out
 
 
+def adjoint_bytes(ndim, L, labels):
+    """Algorithmic HBM bytes per point of one reverse step: the forward state
+    at the step's input read once, the adjoint state (same arrays) read and
+    written once, the medium (kappa0, its nonlinear factor, rho) read once,
+    the gradient accumulator read and written once, plus the 1-byte label."""
+    n_state = 1 + ndim + 2 * ndim * L
+    return 4 * n_state + 8 * n_state + 12 + 8 + (1 if labels else 0)
+
+
+def adjoint_leg(steps=6000, K=64, shot=31, timed_reverse=200):
+    """Gradient of the receiver-trace misfit for one shot of the 1536^2
+    inversion workload: observed traces from the true medium, then the
+    checkpointed forward (one state block every K steps) and the backward
+    (segment recompute + reverse steps).  The reverse step alone is timed
+    with HIP events on the domain's stream for the roofline."""
+    import torch
+    import workloads as W
+    from paper_2106_11476_amd import adjoint, fw2
+    dev = torch.device("cuda:0")
+    prob, c_true = W.inversion_2d(shot=shot, n_steps=steps)
+    truth = W.Problem(**{k: getattr(prob, k) for k in prob.__dataclass_fields__})
+    truth.c = c_true
+    dom = fw2.from_problem(truth, device=dev, cap_steps=steps)
+    dom.step(steps)
+    torch.cuda.synchronize(dev)
+    obs = dom.trace[:steps].clone()
+    dom.destroy_domain()
+    c = torch.tensor(np.asarray(prob.c, np.float64), requires_grad=True)
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
+    J = adjoint.misfit(c, obs, prob, steps, checkpoint_every=K)
+    torch.cuda.synchronize(dev)
+    t1 = time.perf_counter()
+    J.backward()
+    torch.cuda.synchronize(dev)
+    t2 = time.perf_counter()
+    g = c.grad.numpy()
+    # reverse step alone
+    stream = torch.cuda.Stream(device=dev)
+    dom = fw2.from_problem(prob, device=dev, stream=stream, cap_steps=steps)
+    dom.step(400)
+    st = dom.new_state_buffer()
+    dom.save_state(st)
+    res = torch.zeros((1, len(prob.rcv_idx)), device=dev)
+    dom.adjoint_begin()
+    for k in range(20):
+        dom.adjoint_step(st, 399, res[0])
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for k in range(timed_reverse):
+        dom.adjoint_step(st, 399, res[0])
+    e1.record(stream)
+    stream.synchronize()
+    ms = e0.elapsed_time(e1) / timed_reverse
+    dom.destroy_domain()
+    labels = prob.label is not None and np.asarray(prob.relax_table).shape[0] > 1
+    b = adjoint_bytes(prob.ndim, prob.n_relax, labels)
+    gbs = b * prob.npts / (ms * 1e-3) / 1e9
+    return {"workload": prob.name, "grid": list(prob.shape), "steps": steps, "checkpoint_every": K,
+            "sources_per_shot": 1, "receivers": int(len(prob.rcv_idx)),
+            "misfit": float(J.item()), "gradient_finite": bool(np.isfinite(g).all()),
+            "forward_s": round(t1 - t0, 3), "backward_s": round(t2 - t1, 3),
+            "gradient_s_per_shot": round(t2 - t0, 3),
+            "reverse_step_ms": round(ms, 5),
+            "reverse_gpts": round(prob.npts / (ms * 1e-3) / 1e9, 3),
+            "reverse_roofline": {"bound": "hbm", "alg_bytes_per_point": b, "achieved": round(gbs, 1),
+                                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4)}}
+
+
 def _db_rows(db, sql):
     import sqlite3
     con = sqlite3.connect(db)
@@ -188,7 +259,8 @@ def summarize_profiles(stats_db, fetch_db, write_db, workload, copy_bytes, comma
     w_scale = copy_bytes / 1024.0 / wmax[copy_name][2]
     sha = kernel_source_sha()
     os.makedirs(PROFILES, exist_ok=True)
-    lines = ["rocprofv3 kernel statistics, workload %s" % workload, "commands:"]
+    lines = ["rocprofv3 kernel statistics of the first command (benchmark workload %s; "
+             "kernels of the other legs that command runs are listed too)" % workload, "commands:"]
     lines += ["  " + c for c in commands]
     lines.append("kernel_source_sha256_16: %s" % sha)
     lines.append("%-70s %8s %12s %10s" % ("kernel", "calls", "total_us", "avg_us"))
@@ -200,15 +272,18 @@ def summarize_profiles(stats_db, fetch_db, write_db, workload, copy_bytes, comma
     prob = make_workload(workload) if workload in ("abdominal_2d", "plain_2d") else None
     labels = prob.label is not None and np.asarray(prob.relax_table).shape[0] > 1
     p_b, v_b, _ = kernel_bytes(prob.ndim, prob.n_relax, labels)
+    # the benchmark's sweep kernels carry the mechanism count as their first
+    # template argument (other legs of a run may launch other instances)
+    tag = "<%d, " % prob.n_relax
     for short, key, alg in (("pressure_kernel", "pressure_", p_b), ("velocity_kernel", "velocity_", v_b)):
-        names = [n for n in fmax if key in n]
+        names = [n for n in fmax if key in n and tag in n]
         if not names:
             continue
         n = names[0]
         fk, wk = fmax[n][1], wmax[n][1]
         hbm = int(round((fk * f_scale + wk * w_scale) * 1024))
         algb = alg * prob.npts
-        avg_us = [r[3] for r in stats if key in r[0]]
+        avg_us = [r[3] for r in stats if r[0] == n]
         txt = ["HBM traffic of %s on workload %s" % (n, workload), "commands:"]
         txt += ["  " + c for c in commands]
         txt += ["kernel_source_sha256_16: %s" % sha,
@@ -238,6 +313,8 @@ def main():
     ap.add_argument("--n3d", type=int, default=1024, help="cube side of the skull_3d workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true", help="skip the batched-serving leg")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint (gradient) leg")
+    ap.add_argument("--adjoint-steps", type=int, default=6000, help="steps of the adjoint leg's shot")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first time a plain device copy of this size (bandwidth reference, "
                          "and the known-size kernel for scaling HBM counters)")
@@ -311,6 +388,8 @@ def main():
     dom.destroy_domain()
     if not args.no_serving and args.workload != "skull_3d":
         out["serving"] = serving_leg()
+    if not args.no_adjoint and args.workload != "skull_3d":
+        out["adjoint"] = adjoint_leg(steps=args.adjoint_steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob)
     print(json.dumps(out), flush=True)

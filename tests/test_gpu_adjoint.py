@@ -178,3 +178,60 @@ def test_printed_scheme_is_rejected_and_c_library_checks_state():
     with pytest.raises(fw2.Fw2Error, match="UNSUPPORTED"):
         dom.adjoint_begin()
     dom.destroy_domain()
+
+
+def test_full_size_inversion_shot_matches_central_differences():
+    """The 1536^2 inversion workload, one shot, 6000 steps, checkpoints every
+    64 steps (the configuration the benchmark times): the directional
+    derivative along the true blob perturbation and along bumps at depth
+    matches central differences of the GPU misfit (the property holds at any
+    size; the FP64 oracle cannot store this run).
+
+    The central difference carries an O(eps^2) error set by the third
+    derivative of J; next to the array, where the direct wave is large, that
+    term dominates at any eps the FP32 misfit can resolve, so the difference
+    is Richardson-extrapolated from eps and eps/2 (which removes it) and the
+    directions are ones whose first-order change of J stands well above the
+    FP32 rounding of J (taken as 1e-6 J)."""
+    torch = _torch()
+    from paper_2106_11476_amd import adjoint, fw2
+    n_steps = 6000
+    prob, c_true = W.inversion_2d(shot=31, n_steps=n_steps)
+    _say("adjoint full size", prob.shape, "steps", n_steps, "K 64")
+    truth = W.Problem(**{k: getattr(prob, k) for k in prob.__dataclass_fields__})
+    truth.c = c_true
+    dom = fw2.from_problem(truth, device="cuda:0", cap_steps=n_steps)
+    dom.step(n_steps)
+    torch.cuda.synchronize()
+    obs = dom.trace[:n_steps].clone()
+    dom.destroy_domain()
+    c = torch.tensor(np.asarray(prob.c, np.float64), requires_grad=True)
+    J = adjoint.misfit(c, obs, prob, n_steps, checkpoint_every=64)
+    J.backward()
+    J0, g = float(J.item()), c.grad.numpy()
+    assert np.isfinite(g).all() and J0 > 0
+    n = prob.shape[0]
+    yy, xx = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    rx, ry = int(prob.rcv_idx[200] % n), int(prob.rcv_idx[200] // n)
+
+    def bump(x, y, w):
+        return np.exp(-((xx - x) ** 2 + (yy - y) ** 2) / (2 * w * w))
+
+    dirs = [("blobs", np.asarray(c_true, np.float64) - np.asarray(prob.c, np.float64)),
+            ("bump below receiver 200", bump(rx, ry + 300, 12.0)),
+            ("bump at the centre", bump(n // 2, n // 2 - 68, 30.0))]
+    noise = 1e-6 * J0
+
+    def J_at(cc):
+        with torch.no_grad():
+            return float(adjoint.misfit(torch.tensor(cc), obs, prob, n_steps).item())
+
+    for name, dc in dirs:
+        dc = dc / np.abs(dc).max()
+        dd = float(np.sum(g * dc))
+        eps = min(1e-2 * J0 / abs(dd), 5.0)
+        assert 2 * (eps / 2) * abs(dd) >= 100 * noise, (name, "direction too weak for FP32 differences")
+        fd = [(J_at(prob.c + e * dc) - J_at(prob.c - e * dc)) / (2 * e) for e in (eps, eps / 2)]
+        fd_r = (4 * fd[1] - fd[0]) / 3
+        _say(name, "eps %.3g fd %.6e %.6e extrapolated %.6e adjoint %.6e" % (eps, fd[0], fd[1], fd_r, dd))
+        assert abs(fd_r - dd) <= 1e-2 * abs(dd) + 1.5 * noise / (eps / 2), (name, fd_r, dd)

@@ -402,3 +402,51 @@ def serving_requests(n=256, seed=4, sides=(1024, 3072), side_step=256, f0_range=
             t += rng.exponential(1.0 / rate)
         out.append((prob, steps, t if rate else 0.0))
     return out
+
+
+# ---------------------------------------------------------------------------
+# Workload 5: 2D sound-speed inversion (gradient of a trace misfit), L = 2
+# ---------------------------------------------------------------------------
+
+def inversion_2d(n=1536, seed=5, shot=0, n_steps=6000, ppw=12, f0=2e6, cfl=0.4, L=2,
+                 n_src=64, n_rcv=256, n_blobs=8, blob_amp=0.03):
+    """One shot of a seeded inversion problem on an n x n grid (including the
+    4-wavelength boundary layers).  The background is the layered abdominal
+    recipe at f0 without scatterers; the true medium multiplies its sound
+    speed by (1 + sum_k s_k blob_amp G_k) with n_blobs Gaussian blobs G_k
+    (peak 1, radius 0.02-0.06 of the interior, signs s_k = +-1) inside the
+    interior.  n_src point sources sit on one row 8 cells below the top
+    boundary layer, evenly spaced across the interior; this problem fires
+    source `shot` with a 3-cycle pulse (1e5 Pa).  n_rcv receivers sit on the
+    same row.  The stencil's Courant number and the boundary layer's speed
+    are fixed from the background (they do not vary with c), and the time
+    step keeps the true medium at the stated CFL.  Returns (problem with the
+    background c, true c)."""
+    prob = abdominal_2d(nx=n, ny=n, seed=seed, n_steps=n_steps, ppw=ppw, f0=f0, cfl=cfl,
+                        n_scatter=0, n_elem=1, L=L)
+    rng = np.random.default_rng(seed + 1000)
+    nb = prob.bound_cells[0]
+    inner = n - 2 * nb
+    yy, xx = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    pert = np.zeros((n, n))
+    for _ in range(n_blobs):
+        r = rng.uniform(0.02, 0.06) * inner
+        cx, cy = rng.uniform(nb + 2 * r, n - nb - 2 * r, 2)
+        s = 1.0 if rng.random() < 0.5 else -1.0
+        pert += s * np.exp(-((xx - cx) ** 2 + (yy - cy) ** 2) / (2 * r * r))
+    c_bg = np.asarray(prob.c, np.float64)
+    c_true = (c_bg * (1.0 + blob_amp * pert)).astype(np.float32)
+    prob.dt = cfl * prob.h / float(c_true.max())
+    prob.fd_r = float(c_true.max()) * prob.dt / prob.h
+    prob.pml_cp = float(c_bg.max())
+    ey = nb + 8
+    sx = nb + (np.arange(n_src) * inner) // n_src + inner // (2 * n_src)
+    rx = nb + (np.arange(n_rcv) * inner) // n_rcv + inner // (2 * n_rcv)
+    prob.src_idx = prob.flat(np.array([sx[shot]]), np.array([ey]))
+    prob.src_sig = np.zeros(1, np.int32)
+    prob.src_w = np.ones(1, np.float32)
+    nt = pulse_length(prob.dt, f0, 3)
+    prob.signals = gaussian_pulse(nt, prob.dt, f0, 3, amp=1e5)[None, :]
+    prob.rcv_idx = prob.flat(rx, np.full_like(rx, ey))
+    prob.name = "inversion_2d_%d_shot%d" % (n, shot)
+    return prob, c_true
