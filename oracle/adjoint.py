@@ -202,6 +202,8 @@ def misfit_and_gradient(prob, obs, n_steps, maps=None):
         maps = solver.coefficient_maps(prob)
     if maps.scheme != 1:
         raise ValueError("the adjoint is derived for the time-centred memory scheme")
+    if maps.stencil_mode != 0:
+        raise ValueError("the adjoint is derived for one global stencil")
     st = solver.State(maps.ndim, maps.L, maps.grid)
     states, traces = [], []
     for n in range(n_steps):

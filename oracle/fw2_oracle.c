@@ -8,6 +8,9 @@
  * 1/kappa, staggered medium values) is prepared by oracle/solver.py from the
  * paper's formulas and handed in as arrays; this file only advances the state.
  *
+ * The stencil weights are either one global set or, in stencil mode 1, the
+ * set of the local Courant number at each p and v point (gw_p, gw_v).
+ *
  * One time step (Sec. 3.1 staggered scheme, Eqs. general5 and general6):
  *   1. pressure phase, every p point (integer position along each axis):
  *        D_a    = (D^- v_a)                       stencil of Sec. 3.1
@@ -61,6 +64,11 @@ typedef struct {
     const double *signals;   /* [n_sig][n_t] */
     int32_t n_rcv;
     const int64_t *rcv_idx;
+    /* Per-point stencil weights (stencil mode 1), or NULL for the global g:
+     * gw_p [5][npts] at p points, gw_v [ndim][5][npts] at v_a points; rows
+     * g_10 .. g_40, g_11, all over h. */
+    const double *gw_p;
+    const double *gw_v;
 } oracle_problem;
 
 /* Field value at integer coordinate x (x[0] fastest); zero outside the grid. */
@@ -81,34 +89,42 @@ static double at_shift(const double *f, const int64_t *n, const int64_t *x,
     return at(f, n, y);
 }
 
+/* Stencil weights (g_10..g_40, g_11, over h) that apply at flat index idx:
+ * the global set, or row k of the per-point table tab ([5][npts]). */
+static void weights_at(const oracle_problem *P, const double *tab, int64_t npts, int64_t idx, double w[5])
+{
+    for (int k = 0; k < 5; ++k)
+        w[k] = tab ? tab[k * npts + idx] : (k < 4 ? P->g[k] : P->g11);
+}
+
 /* (D^- v_a) at the p point x: v_a[k] sits at k + 1/2 along a. */
-static double d_minus(const oracle_problem *P, const double *va, int a, const int64_t *x)
+static double d_minus(const oracle_problem *P, const double *w, const double *va, int a, const int64_t *x)
 {
     double s = 0.0;
     for (int m = 1; m <= 4; ++m)
-        s += P->g[m - 1] * (at_shift(va, P->n, x, a, m - 1, -1, 0) -
-                            at_shift(va, P->n, x, a, -m, -1, 0));
+        s += w[m - 1] * (at_shift(va, P->n, x, a, m - 1, -1, 0) -
+                         at_shift(va, P->n, x, a, -m, -1, 0));
     for (int b = 0; b < P->ndim; ++b) {
         if (b == a) continue;
         for (int sg = -1; sg <= 1; sg += 2)
-            s += P->g11 * (at_shift(va, P->n, x, b, sg, -1, 0) -
-                           at_shift(va, P->n, x, a, -1, b, sg));
+            s += w[4] * (at_shift(va, P->n, x, b, sg, -1, 0) -
+                         at_shift(va, P->n, x, a, -1, b, sg));
     }
     return s;
 }
 
 /* (D^+ p)_a at the v_a point x (position x + 1/2 e_a). */
-static double d_plus(const oracle_problem *P, const double *p, int a, const int64_t *x)
+static double d_plus(const oracle_problem *P, const double *w, const double *p, int a, const int64_t *x)
 {
     double s = 0.0;
     for (int m = 1; m <= 4; ++m)
-        s += P->g[m - 1] * (at_shift(p, P->n, x, a, m, -1, 0) -
-                            at_shift(p, P->n, x, a, -(m - 1), -1, 0));
+        s += w[m - 1] * (at_shift(p, P->n, x, a, m, -1, 0) -
+                         at_shift(p, P->n, x, a, -(m - 1), -1, 0));
     for (int b = 0; b < P->ndim; ++b) {
         if (b == a) continue;
         for (int sg = -1; sg <= 1; sg += 2)
-            s += P->g11 * (at_shift(p, P->n, x, a, 1, b, sg) -
-                           at_shift(p, P->n, x, b, sg, -1, 0));
+            s += w[4] * (at_shift(p, P->n, x, a, 1, b, sg) -
+                         at_shift(p, P->n, x, b, sg, -1, 0));
     }
     return s;
 }
@@ -127,8 +143,10 @@ static void pressure_phase(const oracle_problem *P, double *p, const double *v, 
             x[0] = i;
             const int64_t idx = row * nx + i;
             double S = 0.0;
+            double w[5];
+            weights_at(P, P->gw_p, npts, idx, w);
             for (int a = 0; a < P->ndim; ++a) {
-                const double D = d_minus(P, v + a * npts, a, x);
+                const double D = d_minus(P, w, v + a * npts, a, x);
                 double acc = 0.0;
                 for (int nu = 0; nu < L; ++nu) {
                     const int64_t c = ((int64_t)a * L + nu) * npts + idx;
@@ -165,7 +183,9 @@ static void velocity_phase(const oracle_problem *P, const double *p, double *v, 
             const int64_t idx = row * nx + i;
             for (int a = 0; a < P->ndim; ++a) {
                 if (x[a] == P->n[a] - 1) continue;   /* outside the grid */
-                const double D = d_plus(P, p, a, x);
+                double w[5];
+                weights_at(P, P->gw_v ? P->gw_v + (int64_t)a * 5 * npts : NULL, npts, idx, w);
+                const double D = d_plus(P, w, p, a, x);
                 double acc = 0.0;
                 for (int nu = 0; nu < L; ++nu) {
                     const int64_t c = ((int64_t)a * L + nu) * npts + idx;

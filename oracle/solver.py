@@ -31,7 +31,9 @@ sample past the last pressure sample is outside the grid and stays zero), so
 the staggered grid is mirror symmetric; the momentum multiplier uses the mean
 of the two neighbouring pressures at the current level, the mass multiplier the pressure of the previous level; fields
 are zero outside the grid; sources add to p after the pressure phase and
-receivers read p after the sources.
+receivers read p after the sources; with stencil_mode 1 the stencil weights
+are those of the local Courant number (pressure point: its cell; v point: the
+mean of the two cells' r^2).
 """
 import ctypes
 import os
@@ -70,6 +72,7 @@ class _Problem(ctypes.Structure):
         ("n_src", ctypes.c_int32), ("src_idx", ctypes.c_void_p), ("src_sig", ctypes.c_void_p),
         ("src_w", ctypes.c_void_p), ("n_t", ctypes.c_int32), ("signals", ctypes.c_void_p),
         ("n_rcv", ctypes.c_int32), ("rcv_idx", ctypes.c_void_p),
+        ("gw_p", ctypes.c_void_p), ("gw_v", ctypes.c_void_p),
     ]
 
 
@@ -150,6 +153,23 @@ def coefficient_maps(prob):
     r = float(prob.fd_r) if prob.fd_r and prob.fd_r > 0 else cmax * m.dt / m.h
     g, g11 = stencil.stencil_weights(r, ndim)
     m.r, m.g, m.g11 = r, g / m.h, g11 / m.h
+    # stencil_mode 1: the weights of the local Courant number at every point.
+    # A pressure point takes r^2 = (c dt / h)^2 of its cell; a v_a point the
+    # mean of the r^2 of the two cells it lies between (the cell past the
+    # last one repeating the last value).  Rows: g_10..g_40, g_11, over h.
+    m.stencil_mode = int(getattr(prob, "stencil_mode", 0))
+    m.gw_p = m.gw_v = None
+    if m.stencil_mode == 1:
+        r2 = (c * m.dt / m.h) ** 2
+        gp, g11p = stencil.local_weights(r2, ndim)
+        m.gw_p = np.concatenate([gp, g11p[None]]) / m.h
+        gv = []
+        for a in range(ndim):
+            ga, g11a = stencil.local_weights(0.5 * (r2 + _next_along(r2, ndim, a)), ndim)
+            gv.append(np.concatenate([ga, g11a[None]]) / m.h)
+        m.gw_v = np.stack(gv)
+    elif m.stencil_mode != 0:
+        raise ValueError("stencil_mode must be 0 or 1")
 
     # Relaxation tuple per point.
     table = np.asarray(prob.relax_table, dtype=np.float64)
@@ -260,6 +280,8 @@ def run(prob, n_steps, state=None, maps=None, record=True):
     P.signals = ptr(signals)
     P.n_rcv = int(ridx.size)
     P.rcv_idx = ptr(ridx, np.int64)
+    P.gw_p = ptr(maps.gw_p) if maps.gw_p is not None else None
+    P.gw_v = ptr(maps.gw_v) if maps.gw_v is not None else None
     for name in ("p", "v", "psi1", "psi2"):
         arr = getattr(state, name)
         if not (arr.flags.c_contiguous and arr.dtype == np.float64):
@@ -325,6 +347,13 @@ def numpy_run(prob, n_steps, state=None, maps=None):
     def add(o1, o2):
         return [o1[k] + o2[k] for k in range(3)]
 
+    if maps.stencil_mode == 1:
+        wp = [maps.gw_p[k] for k in range(5)]
+        wv = [[maps.gw_v[a, k] for k in range(5)] for a in range(ndim)]
+    else:
+        wp = list(maps.g) + [maps.g11]
+        wv = [wp] * ndim
+
     for s in range(int(n_steps)):
         step = state.step
         # pressure phase
@@ -333,14 +362,14 @@ def numpy_run(prob, n_steps, state=None, maps=None):
             vp = _pad(state.v[a])
             D = np.zeros(grid)
             for mm in range(1, 5):
-                D += maps.g[mm - 1] * (_shift(vp, ndim, grid, e(a, mm - 1)) -
-                                       _shift(vp, ndim, grid, e(a, -mm)))
+                D += wp[mm - 1] * (_shift(vp, ndim, grid, e(a, mm - 1)) -
+                                   _shift(vp, ndim, grid, e(a, -mm)))
             for b in range(ndim):
                 if b == a:
                     continue
                 for sg in (-1, 1):
-                    D += maps.g11 * (_shift(vp, ndim, grid, e(b, sg)) -
-                                     _shift(vp, ndim, grid, add(e(a, -1), e(b, sg))))
+                    D += wp[4] * (_shift(vp, ndim, grid, e(b, sg)) -
+                                  _shift(vp, ndim, grid, add(e(a, -1), e(b, sg))))
             acc = np.zeros(grid)
             for nu in range(L):
                 acc += _memory(maps.scheme, state.psi2, a, nu, maps.a2, maps.b2, maps.e0_2, D)
@@ -358,13 +387,13 @@ def numpy_run(prob, n_steps, state=None, maps=None):
         for a in range(ndim):
             D = np.zeros(grid)
             for mm in range(1, 5):
-                D += maps.g[mm - 1] * (_shift(pp, ndim, grid, e(a, mm)) -
-                                       _shift(pp, ndim, grid, e(a, -(mm - 1))))
+                D += wv[a][mm - 1] * (_shift(pp, ndim, grid, e(a, mm)) -
+                                      _shift(pp, ndim, grid, e(a, -(mm - 1))))
             for b in range(ndim):
                 if b == a:
                     continue
                 for sg in (-1, 1):
-                    D += maps.g11 * (_shift(pp, ndim, grid, add(e(a, 1), e(b, sg))) -
+                    D += wv[a][4] * (_shift(pp, ndim, grid, add(e(a, 1), e(b, sg))) -
                                      _shift(pp, ndim, grid, e(b, sg)))
             acc = np.zeros(grid)
             psi1_old[a] = [state.psi1[a, nu].copy() for nu in range(L)]

@@ -16,6 +16,12 @@ global Courant number r = c_ref dt / h:
 * mixed fourth-order term theta_x^2 theta_y^2: g_11 = r^2 / 24.
 
 At r = 0 this is the textbook eighth-order staggered set.
+
+The paper's scheme comes from a time-space domain design whose weights depend
+on the Courant number, i.e. on the velocity.  With stencil_mode 1 every point
+takes the weights of its own Courant number r = c dt / h (the same Taylor
+conditions solved at that r; local_weights below), instead of one r for the
+whole grid.
 """
 import numpy as np
 
@@ -36,6 +42,24 @@ def stencil_weights(r: float, ndim: int):
     rhs = np.array([float(r) ** (2 * kk - 2) for kk in k])
     c = np.linalg.solve(A, rhs)
     g11 = float(r) ** 2 / 24.0
+    g = c.copy()
+    g[0] = c[0] - 2.0 * (ndim - 1) * g11
+    return g, g11
+
+
+def local_weights(r2, ndim: int):
+    """Weights of stencil_weights for every entry of an array of r^2 values.
+
+    Returns (g, g11) with g of shape (4,) + r2.shape: the Taylor conditions
+    of stencil_weights solved at each r (one solve of the same 4 x 4 system
+    with one right-hand side per point)."""
+    r2 = np.asarray(r2, dtype=np.float64)
+    k = np.arange(1, M + 1)
+    j = np.arange(1, M + 1)
+    A = np.array([[(2.0 * jj - 1.0) ** (2 * kk - 1) for jj in j] for kk in k])
+    rhs = np.stack([r2.ravel() ** (kk - 1) for kk in k])        # r^(2k-2)
+    c = np.linalg.solve(A, rhs).reshape((M,) + r2.shape)
+    g11 = r2 / 24.0
     g = c.copy()
     g[0] = c[0] - 2.0 * (ndim - 1) * g11
     return g, g11

@@ -76,6 +76,7 @@ class Problem:
     pml_cp: float = 0.0                      # 0: largest c of the map
     fd_r: float = 0.0                        # 0: largest c * dt / h
     relax_scheme: int = 1                    # 0: printed recursion, 1: time-centred
+    stencil_mode: int = 0                    # 0: one global r, 1: r of the local sound speed
     src_idx: np.ndarray = field(default_factory=lambda: np.zeros(0, np.int64))
     src_sig: np.ndarray = field(default_factory=lambda: np.zeros(0, np.int32))
     src_w: np.ndarray = field(default_factory=lambda: np.zeros(0, np.float32))
