@@ -11,8 +11,8 @@ the dominant kernel (HIP-event durations on the domain's stream, algorithmic
 bytes per launch), batched-serving sims/s and p50/p99 latency against the
 plain one-at-a-time solver, the sound-speed gradient of one shot of the
 1536^2 inversion workload (checkpointed forward + reverse steps, with the
-reverse step's own roofline), and the FP64 CPU oracle timed on a bounded
-sample.
+reverse step's own roofline), the same workload with per-point stencil
+weights, and the FP64 CPU oracle timed on a bounded sample.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload abdominal_2d|plain_2d|skull_3d]
 """
@@ -165,6 +165,44 @@ def serving_leg(seed=4):
     return out
 
 
+def local_stencil_leg(prob, steps, warmup=20):
+    """The benchmark workload with per-point stencil weights (every point the
+    weights of its own Courant number): Gpoint-updates/s and both kernels'
+    HIP-event durations.  The pressure kernel then also reads rho (+4 B per
+    point); the step's algorithmic bytes are unchanged (rho is read once per
+    step already)."""
+    import torch
+    from paper_2106_11476_amd import fw2
+    dev = torch.device("cuda:0")
+    loc = type(prob)(**{k: getattr(prob, k) for k in prob.__dataclass_fields__})
+    loc.stencil_mode = fw2.STENCIL_LOCAL
+    stream = torch.cuda.Stream(device=dev)
+    dom = fw2.from_problem(loc, device=dev, stream=stream, cap_steps=steps + warmup)
+    dom.step(warmup)
+    torch.cuda.synchronize(dev)
+    dom.enable_kernel_timing(True)
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
+    dom.step(steps)
+    torch.cuda.synchronize(dev)
+    el = time.perf_counter() - t0
+    ms, cnt = dom.get_kernel_timing()
+    dom.check_finite(1e9)
+    dom.destroy_domain()
+    labels = prob.label is not None and np.asarray(prob.relax_table).shape[0] > 1
+    p_b, v_b, step_b = kernel_bytes(prob.ndim, prob.n_relax, labels)
+    p_b += 4
+    avg = [ms[0] / max(cnt[0], 1), ms[1] / max(cnt[1], 1)]
+    gpts = prob.npts * steps / el / 1e9
+    return {"steps": steps, "value": round(gpts, 3), "unit": "Gpoint-updates/s",
+            "ms_per_step": round(el / steps * 1e3, 5),
+            "pressure_kernel": {"launch_ms": round(avg[0], 5), "alg_bytes_per_point": p_b,
+                                "frac": round(p_b * prob.npts / (avg[0] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+            "velocity_kernel": {"launch_ms": round(avg[1], 5), "alg_bytes_per_point": v_b,
+                                "frac": round(v_b * prob.npts / (avg[1] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+            "step_frac": round(gpts * step_b / HBM_PEAK_GBS, 4)}
+
+
 def adjoint_bytes(ndim, L, labels):
     """Algorithmic HBM bytes per point of one reverse step: the forward state
     at the step's input read once, the adjoint state (same arrays) read and
@@ -315,6 +353,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the batched-serving leg")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint (gradient) leg")
     ap.add_argument("--adjoint-steps", type=int, default=6000, help="steps of the adjoint leg's shot")
+    ap.add_argument("--no-local-stencil", action="store_true",
+                    help="skip the leg with per-point stencil weights")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first time a plain device copy of this size (bandwidth reference, "
                          "and the known-size kernel for scaling HBM counters)")
@@ -386,6 +426,8 @@ def main():
     if copy_probe is not None:
         out["copy_probe"] = copy_probe
     dom.destroy_domain()
+    if not args.no_local_stencil:
+        out["local_stencil"] = local_stencil_leg(prob, max(1, min(K, 2000)))
     if not args.no_serving and args.workload != "skull_3d":
         out["serving"] = serving_leg()
     if not args.no_adjoint and args.workload != "skull_3d":

@@ -68,6 +68,18 @@ enum { FW2_HOST = 0, FW2_DEVICE = 1 };
  *     fifth of the attenuation at 12 points per wavelength, CFL 0.4. */
 enum { FW2_RELAX_PRINTED = 0, FW2_RELAX_CENTRED = 1 };
 
+/* Stencil weights (Sec. 3.1: the (8,4) operator of a time-space design whose
+ * weights depend on the Courant number r = c dt / h).
+ *   FW2_STENCIL_GLOBAL: one set for the grid, at r = fd_r (or max(c) dt / h).
+ *   FW2_STENCIL_LOCAL: every point uses the set of its own r: a pressure
+ *     point r^2 = (c dt / h)^2 of its cell, a velocity point the mean of the
+ *     r^2 of the two cells it lies between.  The weights are fixed cubic
+ *     polynomials in r^2 (the Taylor conditions are linear in the weights
+ *     with right-hand side 1, r^2, r^4, r^6), evaluated in the kernels from
+ *     rho and kappa0; fd_r is then unused.  Not available to the batched
+ *     path or the adjoint (FW2_E_UNSUPPORTED there). */
+enum { FW2_STENCIL_GLOBAL = 0, FW2_STENCIL_LOCAL = 1 };
+
 typedef struct {
     int32_t ndim;             /* 2 or 3 */
     int32_t n_relax;          /* L, 1..FW2_MAX_RELAX */
@@ -81,6 +93,7 @@ typedef struct {
     double pml_cp;            /* c_p of Table 1's d target; <= 0: largest c of the map */
     double fd_r;              /* Courant number of the (8,4) weights; <= 0: max(c) dt / h */
     int32_t relax_scheme;     /* FW2_RELAX_PRINTED or FW2_RELAX_CENTRED */
+    int32_t stencil_mode;     /* FW2_STENCIL_GLOBAL or FW2_STENCIL_LOCAL */
     const float *c;           /* host [nz][ny][nx] sound speed (m/s), > 0 */
     const float *rho;         /* host [nz][ny][nx] equilibrium density rho_0 (kg/m^3), > 0 */
     const float *beta;        /* host [nz][ny][nx] coefficient of nonlinearity 1 + B/2A */

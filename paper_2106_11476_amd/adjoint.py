@@ -54,6 +54,8 @@ def _misfit_function():
             K = max(1, min(K, n))
             if prob.relax_scheme != fw2.RELAX_CENTRED:
                 raise fw2.Fw2Error(6, "the adjoint is derived for the time-centred memory scheme")
+            if getattr(prob, "stencil_mode", fw2.STENCIL_GLOBAL) != fw2.STENCIL_GLOBAL:
+                raise fw2.Fw2Error(6, "the adjoint is derived for global stencil weights")
             p = _problem_with_c(prob, c.detach().cpu().numpy())
             dev = obs.device
             dom = fw2.Domain(p, device=dev, stream=torch.cuda.current_stream(dev))

@@ -75,6 +75,8 @@ fw2_status validate_scalars(const fw2_domain_desc *d)
     if (!std::isfinite(d->pml_cp) || !std::isfinite(d->fd_r)) return fail(FW2_E_INVALID, "non-finite pml_cp/fd_r");
     if (d->relax_scheme != FW2_RELAX_PRINTED && d->relax_scheme != FW2_RELAX_CENTRED)
         return fail(FW2_E_INVALID, "relax_scheme must be 0 or 1");
+    if (d->stencil_mode != FW2_STENCIL_GLOBAL && d->stencil_mode != FW2_STENCIL_LOCAL)
+        return fail(FW2_E_INVALID, "stencil_mode must be 0 or 1");
     if (d->n_labels < 1 || d->n_labels > FW2_MAX_LABELS) return fail(FW2_E_INVALID, "n_labels must be in 1..256");
     if (!d->c || !d->rho || !d->beta || !d->relax_table) return fail(FW2_E_INVALID, "NULL map or table");
     const int L = d->n_relax, row = 2 + 4 * L;
@@ -131,6 +133,29 @@ double max_c(const fw2_domain_desc *d, int64_t npts)
     double m = 0.0;
     for (int64_t q = 0; q < npts; ++q) m = std::max(m, (double)d->c[q]);
     return m;
+}
+
+double min_c(const fw2_domain_desc *d, int64_t npts)
+{
+    double m = HUGE_VAL;
+    for (int64_t q = 0; q < npts; ++q) m = std::min(m, (double)d->c[q]);
+    return m;
+}
+
+// Per-point weights: every point's r lies in [min c, max c] dt / h (a
+// velocity point's r^2 is a mean of two cells'), so the scheme is checked
+// at a sweep of r over that range with the weights of each r.
+bool local_stencil_stable(const fw2_domain_desc *d, int64_t npts)
+{
+    const double r0 = min_c(d, npts) * d->dt / d->h, r1 = max_c(d, npts) * d->dt / d->h;
+    const int K = 16;
+    for (int k = 0; k <= K; ++k) {
+        const double r = std::sqrt(r0 * r0 + (r1 * r1 - r0 * r0) * k / K);
+        double gw[4], g11;
+        fw2::stencil_weights(r, d->ndim, gw, &g11);
+        if (fw2::stability_factor(r, d->ndim, gw, g11) >= 1.0) return false;
+    }
+    return true;
 }
 
 struct TimingSlot {
@@ -339,7 +364,8 @@ fw2_status fw2_create_domain(const fw2_domain_desc *desc, void *dev_workspace, u
     double gw[4], g11;
     fw2::stencil_weights(r, nd, gw, &g11);
     const double r_run = cmax * desc->dt / desc->h;
-    if (fw2::stability_factor(r_run, nd, gw, g11) >= 1.0)
+    if (desc->stencil_mode == FW2_STENCIL_GLOBAL ? fw2::stability_factor(r_run, nd, gw, g11) >= 1.0
+                                                 : !local_stencil_stable(desc, npts))
         return fail(FW2_E_INVALID, "time step above the stability limit of the (8,4) scheme");
 
     fw2_domain *d = new (std::nothrow) fw2_domain();
@@ -385,6 +411,15 @@ fw2_status fw2_create_domain(const fw2_domain_desc *desc, void *dev_workspace, u
     for (int k = 0; k < 4; ++k) a.g[k] = (float)(gw[k] / desc->h);
     a.g11 = (float)(g11 / desc->h);
     a.dt = (float)desc->dt;
+    a.local_stencil = desc->stencil_mode == FW2_STENCIL_LOCAL ? 1 : 0;
+    {
+        double pw[4][4], g11s;
+        fw2::stencil_polynomials(nd, pw, &g11s);
+        for (int j = 0; j < 4; ++j)
+            for (int k = 0; k < 4; ++k) a.pw[j][k] = (float)(pw[j][k] / desc->h);
+        a.g11s = (float)(g11s / desc->h);
+        a.q2 = (float)((desc->dt / desc->h) * (desc->dt / desc->h));
+    }
 
     // Medium planes: kappa0 = 1/(rho c^2), kappa0 (1 - 2 beta), rho (FP64, stored FP32).
     {
@@ -674,6 +709,8 @@ fw2_status fw2_adjoint_begin(fw2_domain *d, void *dev_workspace, uint64_t bytes)
     if (!d) return fail(FW2_E_STATE, "domain is NULL");
     if (d->desc.relax_scheme != FW2_RELAX_CENTRED)
         return fail(FW2_E_UNSUPPORTED, "the adjoint is derived for the time-centred memory scheme");
+    if (d->desc.stencil_mode != FW2_STENCIL_GLOBAL)
+        return fail(FW2_E_UNSUPPORTED, "the adjoint is derived for global stencil weights");
     uint64_t need = 0;
     fw2_status st = fw2_adjoint_workspace_bytes(d, &need);
     if (st != FW2_OK) return st;
@@ -842,6 +879,8 @@ fw2_status fw2_batch_set_domains(fw2_batch *b, int32_t n, fw2_domain *const *dom
         const fw2_domain *d = domains[k];
         if (!d) return fail(FW2_E_INVALID, "NULL domain");
         if (d->desc.ndim != 2) return fail(FW2_E_UNSUPPORTED, "batched stepping is 2D only");
+        if (d->desc.stencil_mode != FW2_STENCIL_GLOBAL)
+            return fail(FW2_E_UNSUPPORTED, "batched stepping uses global stencil weights only");
         if (d->step >= n_steps[k]) return fail(FW2_E_INVALID, "domain already at or past its n_steps");
         for (int32_t q = 0; q < k; ++q)
             if (domains[q] == d) return fail(FW2_E_INVALID, "domain listed twice");

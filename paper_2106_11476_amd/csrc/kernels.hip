@@ -45,7 +45,33 @@ __device__ __forceinline__ int64_t axis_offset(const Geometry &g, int a)
     return a == 0 ? (int64_t)1 : (a == 1 ? g.pitch : g.plane);
 }
 
-template <int NDIM, int L, bool CENTRED>
+// Stencil weights over h at one point: the global set, or (PP) the set of
+// the point's own r^2 = s, from the fixed polynomials in s.
+struct Wts {
+    float g0, g1, g2, g3, g11;
+};
+
+template <bool PP>
+__device__ __forceinline__ Wts weights(const StepArgs &a, float s)
+{
+    if constexpr (PP) {
+        Wts w;
+        w.g0 = fmaf(fmaf(fmaf(a.pw[0][3], s, a.pw[0][2]), s, a.pw[0][1]), s, a.pw[0][0]);
+        w.g1 = fmaf(fmaf(fmaf(a.pw[1][3], s, a.pw[1][2]), s, a.pw[1][1]), s, a.pw[1][0]);
+        w.g2 = fmaf(fmaf(fmaf(a.pw[2][3], s, a.pw[2][2]), s, a.pw[2][1]), s, a.pw[2][0]);
+        w.g3 = fmaf(fmaf(fmaf(a.pw[3][3], s, a.pw[3][2]), s, a.pw[3][1]), s, a.pw[3][0]);
+        w.g11 = a.g11s * s;
+        return w;
+    } else {
+        (void)s;
+        return Wts{a.g[0], a.g[1], a.g[2], a.g[3], a.g11};
+    }
+}
+
+// r^2 of a cell from its rho and kappa0 (c^2 = 1 / (rho kappa0)).
+__device__ __forceinline__ float cell_r2(const StepArgs &a, float rho, float kap) { return a.q2 / (rho * kap); }
+
+template <int NDIM, int L, bool CENTRED, bool PP>
 __global__ void __launch_bounds__(kBX * kBY) pressure_kernel(const StepArgs a)
 {
     const Geometry &g = a.geo;
@@ -60,15 +86,16 @@ __global__ void __launch_bounds__(kBX * kBY) pressure_kernel(const StepArgs a)
         const int c[3] = {i, j, k};
         const int64_t idx = g.origin + (int64_t)k * g.plane + (int64_t)j * g.pitch + i;
         const int lab = a.label ? (int)a.label[idx] : 0;
+        const Wts W = weights<PP>(a, PP ? cell_r2(a, a.rho[idx], a.kap[idx]) : 0.0f);
         float S = 0.0f;
 #pragma unroll
         for (int ax = 0; ax < NDIM; ++ax) {
             const float *va = a.v + ax * g.stride;
             const int64_t o = axis_offset<NDIM>(g, ax);
-            float D = a.g[0] * (va[idx] - va[idx - o]);
-            D = fmaf(a.g[1], va[idx + o] - va[idx - 2 * o], D);
-            D = fmaf(a.g[2], va[idx + 2 * o] - va[idx - 3 * o], D);
-            D = fmaf(a.g[3], va[idx + 3 * o] - va[idx - 4 * o], D);
+            float D = W.g0 * (va[idx] - va[idx - o]);
+            D = fmaf(W.g1, va[idx + o] - va[idx - 2 * o], D);
+            D = fmaf(W.g2, va[idx + 2 * o] - va[idx - 3 * o], D);
+            D = fmaf(W.g3, va[idx + 3 * o] - va[idx - 4 * o], D);
             float cr = 0.0f;
 #pragma unroll
             for (int bx = 0; bx < NDIM; ++bx) {
@@ -76,7 +103,7 @@ __global__ void __launch_bounds__(kBX * kBY) pressure_kernel(const StepArgs a)
                 const int64_t o2 = axis_offset<NDIM>(g, bx);
                 cr += (va[idx + o2] - va[idx - o + o2]) + (va[idx - o2] - va[idx - o - o2]);
             }
-            D = fmaf(a.g11, cr, D);
+            D = fmaf(W.g11, cr, D);
             const int s = slot_int(c[ax], g.n[ax], a.nb[ax]);
             const int t = s * a.n_labels + lab;
             const float2 *bc = a.bc2[ax] + (int64_t)t * L;
@@ -98,7 +125,7 @@ __global__ void __launch_bounds__(kBX * kBY) pressure_kernel(const StepArgs a)
     }
 }
 
-template <int NDIM, int L, bool CENTRED>
+template <int NDIM, int L, bool CENTRED, bool PP>
 __global__ void __launch_bounds__(kBX * kBY) velocity_kernel(const StepArgs a)
 {
     const Geometry &g = a.geo;
@@ -117,15 +144,18 @@ __global__ void __launch_bounds__(kBX * kBY) velocity_kernel(const StepArgs a)
         const float p0 = p[idx];
         const float r0 = a.rho[idx];
         const float k0 = a.kap[idx];
+        const float s0 = PP ? cell_r2(a, r0, k0) : 0.0f;
 #pragma unroll
         for (int ax = 0; ax < NDIM; ++ax) {
             if (c[ax] == g.n[ax] - 1) continue;          // outside the grid, held at zero
             const int64_t o = axis_offset<NDIM>(g, ax);
             const float p1 = p[idx + o];
-            float D = a.g[0] * (p1 - p0);
-            D = fmaf(a.g[1], p[idx + 2 * o] - p[idx - o], D);
-            D = fmaf(a.g[2], p[idx + 3 * o] - p[idx - 2 * o], D);
-            D = fmaf(a.g[3], p[idx + 4 * o] - p[idx - 3 * o], D);
+            // v point between this cell and the next: mean of the two cells' r^2
+            const Wts W = weights<PP>(a, PP ? 0.5f * (s0 + cell_r2(a, a.rho[idx + o], a.kap[idx + o])) : 0.0f);
+            float D = W.g0 * (p1 - p0);
+            D = fmaf(W.g1, p[idx + 2 * o] - p[idx - o], D);
+            D = fmaf(W.g2, p[idx + 3 * o] - p[idx - 2 * o], D);
+            D = fmaf(W.g3, p[idx + 4 * o] - p[idx - 3 * o], D);
             float cr = 0.0f;
 #pragma unroll
             for (int bx = 0; bx < NDIM; ++bx) {
@@ -133,7 +163,7 @@ __global__ void __launch_bounds__(kBX * kBY) velocity_kernel(const StepArgs a)
                 const int64_t o2 = axis_offset<NDIM>(g, bx);
                 cr += (p[idx + o + o2] - p[idx + o2]) + (p[idx + o - o2] - p[idx - o2]);
             }
-            D = fmaf(a.g11, cr, D);
+            D = fmaf(W.g11, cr, D);
             const int s = slot_half(c[ax], g.n[ax], a.nb[ax]);
             const int t = s * a.n_labels + lab;
             const float2 *bc = a.bc1[ax] + (int64_t)t * L;
@@ -208,12 +238,12 @@ __device__ __forceinline__ int halo_c(int t) { return t < 4 ? t : BX + t; }
 template <int L>
 struct PRow {                 // everything the pressure sweep loads for one row
     float vyn, vxn, hx, hy;   // window row j+3, ring row j+1, halos
-    float p0, k0, q0;
+    float p0, k0, q0, r0;     // r0: rho, loaded for per-point weights only
     int l;
     float m[2][L];
 };
 
-template <int L, int BX>
+template <int L, int BX, bool PP>
 __device__ __forceinline__ void p_load_row(PRow<L> &r, const StepArgs &a, int i, int t, int x0, int j, bool live)
 {
     const Geometry &g = a.geo;
@@ -228,6 +258,7 @@ __device__ __forceinline__ void p_load_row(PRow<L> &r, const StepArgs &a, int i,
         r.p0 = a.p[idx];
         r.k0 = a.kap[idx];
         r.q0 = a.nlq[idx];
+        r.r0 = PP ? a.rho[idx] : 1.0f;
         r.l = a.label ? (int)a.label[idx] : 0;
 #pragma unroll
         for (int ax = 0; ax < 2; ++ax)
@@ -238,7 +269,7 @@ __device__ __forceinline__ void p_load_row(PRow<L> &r, const StepArgs &a, int i,
 
 // One tile (columns x0..x0+BX-1, rows y0..y0+rows-1) of the 2D pressure
 // sweep; sx / sy are the block's LDS rings.
-template <int L, bool CENTRED, int BX, bool PF>
+template <int L, bool CENTRED, int BX, bool PF, bool PP>
 __device__ __forceinline__ void pressure_tile2d(const StepArgs &a, int rows, int x0, int y0,
                                                 float (*sx)[BX + 8], float (*sy)[BX + 2])
 {
@@ -268,10 +299,10 @@ __device__ __forceinline__ void pressure_tile2d(const StepArgs &a, int rows, int
     const int sxs = max(max(a.nb[0] - i, i - (nx - 1 - a.nb[0])), 0);
     const int yend = min(y0 + rows, ny);
     PRow<L> cur, nxt;
-    if (PF) p_load_row<L, BX>(cur, a, i, t, x0, y0, live);
+    if (PF) p_load_row<L, BX, PP>(cur, a, i, t, x0, y0, live);
     for (int j = y0; j < yend; ++j) {
-        if (!PF) p_load_row<L, BX>(cur, a, i, t, x0, j, live);        // rows loaded in turn
-        else if (j + 1 < yend) p_load_row<L, BX>(nxt, a, i, t, x0, j + 1, live);   // next row in flight
+        if (!PF) p_load_row<L, BX, PP>(cur, a, i, t, x0, j, live);        // rows loaded in turn
+        else if (j + 1 < yend) p_load_row<L, BX, PP>(nxt, a, i, t, x0, j + 1, live);   // next row in flight
 #pragma unroll
         for (int k = 0; k < 7; ++k) w[k] = w[k + 1];
         w[7] = cur.vyn;
@@ -281,18 +312,19 @@ __device__ __forceinline__ void pressure_tile2d(const StepArgs &a, int rows, int
         if (t < 2) sy[j % 3][t == 0 ? 0 : BX + 1] = cur.hy;
         lds_sync<BX>();
         if (live) {
+            const Wts W = weights<PP>(a, PP ? cell_r2(a, cur.r0, cur.k0) : 0.0f);
             const float *r0 = sx[j & 3], *rp = sx[(j + 1) & 3], *rm = sx[(j + 3) & 3];
-            float Dx = a.g[0] * (r0[t + 4] - r0[t + 3]);
-            Dx = fmaf(a.g[1], r0[t + 5] - r0[t + 2], Dx);
-            Dx = fmaf(a.g[2], r0[t + 6] - r0[t + 1], Dx);
-            Dx = fmaf(a.g[3], r0[t + 7] - r0[t], Dx);
-            Dx = fmaf(a.g11, (rp[t + 4] - rp[t + 3]) + (rm[t + 4] - rm[t + 3]), Dx);
+            float Dx = W.g0 * (r0[t + 4] - r0[t + 3]);
+            Dx = fmaf(W.g1, r0[t + 5] - r0[t + 2], Dx);
+            Dx = fmaf(W.g2, r0[t + 6] - r0[t + 1], Dx);
+            Dx = fmaf(W.g3, r0[t + 7] - r0[t], Dx);
+            Dx = fmaf(W.g11, (rp[t + 4] - rp[t + 3]) + (rm[t + 4] - rm[t + 3]), Dx);
             const float *c0 = sy[j % 3], *cm = sy[(j + 2) % 3];
-            float Dy = a.g[0] * (w[4] - w[3]);
-            Dy = fmaf(a.g[1], w[5] - w[2], Dy);
-            Dy = fmaf(a.g[2], w[6] - w[1], Dy);
-            Dy = fmaf(a.g[3], w[7] - w[0], Dy);
-            Dy = fmaf(a.g11, (c0[t + 2] - cm[t + 2]) + (c0[t] - cm[t]), Dy);
+            float Dy = W.g0 * (w[4] - w[3]);
+            Dy = fmaf(W.g1, w[5] - w[2], Dy);
+            Dy = fmaf(W.g2, w[6] - w[1], Dy);
+            Dy = fmaf(W.g3, w[7] - w[0], Dy);
+            Dy = fmaf(W.g11, (c0[t + 2] - cm[t + 2]) + (c0[t] - cm[t]), Dy);
             const int sys = max(max(a.nb[1] - j, j - (ny - 1 - a.nb[1])), 0);
             float S = 0.0f;
 #pragma unroll
@@ -353,7 +385,7 @@ __device__ __forceinline__ void v_load_row(VRow<L> &r, const StepArgs &a, int i,
 }
 
 // One tile of the 2D velocity sweep; sp / sr / sk are the block's LDS rings.
-template <int L, bool CENTRED, int BX, bool PF>
+template <int L, bool CENTRED, int BX, bool PF, bool PP>
 __device__ __forceinline__ void velocity_tile2d(const StepArgs &a, int rows, int x0, int y0,
                                                 float (*sp)[BX + 8], float (*sr)[BX + 1], float (*sk)[BX + 1])
 {
@@ -407,13 +439,15 @@ __device__ __forceinline__ void velocity_tile2d(const StepArgs &a, int rows, int
             const int64_t idx = g.origin + (int64_t)j * g.pitch + i;
             const float *r0 = sp[j & 3], *rp = sp[(j + 1) & 3], *rm = sp[(j + 3) & 3];
             const float *rr0 = sr[j % 3], *kk0 = sk[j % 3];
+            const float s0 = PP ? cell_r2(a, rr0[t], kk0[t]) : 0.0f;
             // v_x at (i + 1/2, j)
             if (i < nx - 1) {
-                float D = a.g[0] * (r0[t + 5] - r0[t + 4]);
-                D = fmaf(a.g[1], r0[t + 6] - r0[t + 3], D);
-                D = fmaf(a.g[2], r0[t + 7] - r0[t + 2], D);
-                D = fmaf(a.g[3], r0[t + 8] - r0[t + 1], D);
-                D = fmaf(a.g11, (rp[t + 5] - rp[t + 4]) + (rm[t + 5] - rm[t + 4]), D);
+                const Wts W = weights<PP>(a, PP ? 0.5f * (s0 + cell_r2(a, rr0[t + 1], kk0[t + 1])) : 0.0f);
+                float D = W.g0 * (r0[t + 5] - r0[t + 4]);
+                D = fmaf(W.g1, r0[t + 6] - r0[t + 3], D);
+                D = fmaf(W.g2, r0[t + 7] - r0[t + 2], D);
+                D = fmaf(W.g3, r0[t + 8] - r0[t + 1], D);
+                D = fmaf(W.g11, (rp[t + 5] - rp[t + 4]) + (rm[t + 5] - rm[t + 4]), D);
                 const int tt = sxs * a.n_labels + cur.l;
                 const float2 *__restrict__ bc = a.bc1[0] + (int64_t)tt * L;
                 float S = a.w1[0][tt] * D;
@@ -434,11 +468,13 @@ __device__ __forceinline__ void velocity_tile2d(const StepArgs &a, int rows, int
             // v_y at (i, j + 1/2)
             if (j < ny - 1) {
                 const int sys = max(max(a.nb[1] - j, j - (ny - 2 - a.nb[1])), 0);
-                float D = a.g[0] * (w[4] - w[3]);
-                D = fmaf(a.g[1], w[5] - w[2], D);
-                D = fmaf(a.g[2], w[6] - w[1], D);
-                D = fmaf(a.g[3], w[7] - w[0], D);
-                D = fmaf(a.g11, (rp[t + 5] - r0[t + 5]) + (rp[t + 3] - r0[t + 3]), D);
+                const Wts W = weights<PP>(
+                    a, PP ? 0.5f * (s0 + cell_r2(a, sr[(j + 1) % 3][t], sk[(j + 1) % 3][t])) : 0.0f);
+                float D = W.g0 * (w[4] - w[3]);
+                D = fmaf(W.g1, w[5] - w[2], D);
+                D = fmaf(W.g2, w[6] - w[1], D);
+                D = fmaf(W.g3, w[7] - w[0], D);
+                D = fmaf(W.g11, (rp[t + 5] - r0[t + 5]) + (rp[t + 3] - r0[t + 3]), D);
                 const int tt = sys * a.n_labels + cur.l;
                 const float2 *__restrict__ bc = a.bc1[1] + (int64_t)tt * L;
                 float S = a.w1[1][tt] * D;
@@ -461,23 +497,23 @@ __device__ __forceinline__ void velocity_tile2d(const StepArgs &a, int rows, int
     }
 }
 
-template <int L, bool CENTRED, int BX, bool PF>
+template <int L, bool CENTRED, int BX, bool PF, bool PP>
 __global__ void __launch_bounds__(BX) pressure_sweep2d(const StepArgs a, int rows, int nbx, int nblocks)
 {
     __shared__ float sx[4][BX + 8];     // v_x rows, column c <-> x0 - 4 + c
     __shared__ float sy[3][BX + 2];     // v_y rows, column c <-> x0 - 1 + c
     const int tile = tile_of_block(blockIdx.x, nblocks);
-    pressure_tile2d<L, CENTRED, BX, PF>(a, rows, (tile % nbx) * BX, (tile / nbx) * rows, sx, sy);
+    pressure_tile2d<L, CENTRED, BX, PF, PP>(a, rows, (tile % nbx) * BX, (tile / nbx) * rows, sx, sy);
 }
 
-template <int L, bool CENTRED, int BX, bool PF>
+template <int L, bool CENTRED, int BX, bool PF, bool PP>
 __global__ void __launch_bounds__(BX) velocity_sweep2d(const StepArgs a, int rows, int nbx, int nblocks)
 {
     __shared__ float sp[4][BX + 8];     // p rows, column c <-> x0 - 4 + c
     __shared__ float sr[3][BX + 1];     // rho rows, column c <-> x0 + c
     __shared__ float sk[3][BX + 1];     // kappa0 rows
     const int tile = tile_of_block(blockIdx.x, nblocks);
-    velocity_tile2d<L, CENTRED, BX, PF>(a, rows, (tile % nbx) * BX, (tile / nbx) * rows, sp, sr, sk);
+    velocity_tile2d<L, CENTRED, BX, PF, PP>(a, rows, (tile % nbx) * BX, (tile / nbx) * rows, sp, sr, sk);
 }
 
 // ---------------------------------------------------------------------------
@@ -508,7 +544,7 @@ __device__ __forceinline__ void stage(float *dst, const float *__restrict__ f, c
     }
 }
 
-template <int L, bool CENTRED, int BX, int BY>
+template <int L, bool CENTRED, int BX, int BY, bool PP>
 __global__ void __launch_bounds__(BX *BY) pressure_sweep3d(const StepArgs a, int rows, int nbx, int nby, int nblocks)
 {
     constexpr int NT = BX * BY;
@@ -552,13 +588,14 @@ __global__ void __launch_bounds__(BX *BY) pressure_sweep3d(const StepArgs a, int
         stage<ZW, ZH, NT>(sz[k % 3], vz, g, x0 - 1, y0 - 1, k, tid);
         const float vzn = ldz3(vz, g, i, j, k + 3);
         const int64_t idx = g.origin + (int64_t)k * g.plane + (int64_t)j * g.pitch + i;
-        float p0 = 0.0f, k0 = 1.0f, q0 = 0.0f;
+        float p0 = 0.0f, k0 = 1.0f, q0 = 0.0f, r0 = 1.0f;
         float m[3][L];
         int l = 0;
         if (live) {
             p0 = a.p[idx];
             k0 = a.kap[idx];
             q0 = a.nlq[idx];
+            if (PP) r0 = a.rho[idx];
             l = a.label ? (int)a.label[idx] : 0;
 #pragma unroll
             for (int ax = 0; ax < 3; ++ax)
@@ -570,29 +607,30 @@ __global__ void __launch_bounds__(BX *BY) pressure_sweep3d(const StepArgs a, int
         w[7] = vzn;
         __syncthreads();
         if (live) {
+            const Wts W = weights<PP>(a, PP ? cell_r2(a, r0, k0) : 0.0f);
             const float *X0 = sx[k & 3], *Xp = sx[(k + 1) & 3], *Xm = sx[(k + 3) & 3];
             const int cx = (ty + 1) * XW + tx + 4;          // own sample in the v_x tile
-            float Dx = a.g[0] * (X0[cx] - X0[cx - 1]);
-            Dx = fmaf(a.g[1], X0[cx + 1] - X0[cx - 2], Dx);
-            Dx = fmaf(a.g[2], X0[cx + 2] - X0[cx - 3], Dx);
-            Dx = fmaf(a.g[3], X0[cx + 3] - X0[cx - 4], Dx);
-            Dx = fmaf(a.g11, ((X0[cx + XW] - X0[cx + XW - 1]) + (X0[cx - XW] - X0[cx - XW - 1])) +
+            float Dx = W.g0 * (X0[cx] - X0[cx - 1]);
+            Dx = fmaf(W.g1, X0[cx + 1] - X0[cx - 2], Dx);
+            Dx = fmaf(W.g2, X0[cx + 2] - X0[cx - 3], Dx);
+            Dx = fmaf(W.g3, X0[cx + 3] - X0[cx - 4], Dx);
+            Dx = fmaf(W.g11, ((X0[cx + XW] - X0[cx + XW - 1]) + (X0[cx - XW] - X0[cx - XW - 1])) +
                                  ((Xp[cx] - Xp[cx - 1]) + (Xm[cx] - Xm[cx - 1])), Dx);
             const float *Y0 = sy[k & 3], *Yp = sy[(k + 1) & 3], *Ym = sy[(k + 3) & 3];
             const int cy = (ty + 4) * YW + tx + 1;
-            float Dy = a.g[0] * (Y0[cy] - Y0[cy - YW]);
-            Dy = fmaf(a.g[1], Y0[cy + YW] - Y0[cy - 2 * YW], Dy);
-            Dy = fmaf(a.g[2], Y0[cy + 2 * YW] - Y0[cy - 3 * YW], Dy);
-            Dy = fmaf(a.g[3], Y0[cy + 3 * YW] - Y0[cy - 4 * YW], Dy);
-            Dy = fmaf(a.g11, ((Y0[cy + 1] - Y0[cy + 1 - YW]) + (Y0[cy - 1] - Y0[cy - 1 - YW])) +
+            float Dy = W.g0 * (Y0[cy] - Y0[cy - YW]);
+            Dy = fmaf(W.g1, Y0[cy + YW] - Y0[cy - 2 * YW], Dy);
+            Dy = fmaf(W.g2, Y0[cy + 2 * YW] - Y0[cy - 3 * YW], Dy);
+            Dy = fmaf(W.g3, Y0[cy + 3 * YW] - Y0[cy - 4 * YW], Dy);
+            Dy = fmaf(W.g11, ((Y0[cy + 1] - Y0[cy + 1 - YW]) + (Y0[cy - 1] - Y0[cy - 1 - YW])) +
                                  ((Yp[cy] - Yp[cy - YW]) + (Ym[cy] - Ym[cy - YW])), Dy);
             const float *Z0 = sz[k % 3], *Zm = sz[(k + 2) % 3];
             const int cz = (ty + 1) * ZW + tx + 1;
-            float Dz = a.g[0] * (w[4] - w[3]);
-            Dz = fmaf(a.g[1], w[5] - w[2], Dz);
-            Dz = fmaf(a.g[2], w[6] - w[1], Dz);
-            Dz = fmaf(a.g[3], w[7] - w[0], Dz);
-            Dz = fmaf(a.g11, ((Z0[cz + 1] - Zm[cz + 1]) + (Z0[cz - 1] - Zm[cz - 1])) +
+            float Dz = W.g0 * (w[4] - w[3]);
+            Dz = fmaf(W.g1, w[5] - w[2], Dz);
+            Dz = fmaf(W.g2, w[6] - w[1], Dz);
+            Dz = fmaf(W.g3, w[7] - w[0], Dz);
+            Dz = fmaf(W.g11, ((Z0[cz + 1] - Zm[cz + 1]) + (Z0[cz - 1] - Zm[cz - 1])) +
                                  ((Z0[cz + ZW] - Zm[cz + ZW]) + (Z0[cz - ZW] - Zm[cz - ZW])), Dz);
             const int s2 = max(max(a.nb[2] - k, k - (nz - 1 - a.nb[2])), 0);
             float S = 0.0f;
@@ -621,7 +659,7 @@ __global__ void __launch_bounds__(BX *BY) pressure_sweep3d(const StepArgs a, int
     }
 }
 
-template <int L, bool CENTRED, int BX, int BY>
+template <int L, bool CENTRED, int BX, int BY, bool PP>
 __global__ void __launch_bounds__(BX *BY) velocity_sweep3d(const StepArgs a, int rows, int nbx, int nby, int nblocks)
 {
     constexpr int NT = BX * BY;
@@ -682,36 +720,40 @@ __global__ void __launch_bounds__(BX *BY) velocity_sweep3d(const StepArgs a, int
             const int c = (ty + 4) * PW + tx + 4;           // own sample in the p tile
             const int cr = ty * RW + tx;                    // own sample in the rho tile
             const int s2 = max(max(a.nb[2] - k, k - (nz - 2 - a.nb[2])), 0);
+            const float sc = PP ? cell_r2(a, R0[cr], K0[cr]) : 0.0f;
 #pragma unroll
             for (int ax = 0; ax < 3; ++ax) {
                 if ((ax == 0 && i == nx - 1) || (ax == 1 && j == ny - 1) || (ax == 2 && k == nz - 1)) continue;
                 float D, pbar, rho_a, kap_a;
                 if (ax == 0) {
-                    D = a.g[0] * (P0[c + 1] - P0[c]);
-                    D = fmaf(a.g[1], P0[c + 2] - P0[c - 1], D);
-                    D = fmaf(a.g[2], P0[c + 3] - P0[c - 2], D);
-                    D = fmaf(a.g[3], P0[c + 4] - P0[c - 3], D);
-                    D = fmaf(a.g11, ((P0[c + 1 + PW] - P0[c + PW]) + (P0[c + 1 - PW] - P0[c - PW])) +
+                    const Wts W = weights<PP>(a, PP ? 0.5f * (sc + cell_r2(a, R0[cr + 1], K0[cr + 1])) : 0.0f);
+                    D = W.g0 * (P0[c + 1] - P0[c]);
+                    D = fmaf(W.g1, P0[c + 2] - P0[c - 1], D);
+                    D = fmaf(W.g2, P0[c + 3] - P0[c - 2], D);
+                    D = fmaf(W.g3, P0[c + 4] - P0[c - 3], D);
+                    D = fmaf(W.g11, ((P0[c + 1 + PW] - P0[c + PW]) + (P0[c + 1 - PW] - P0[c - PW])) +
                                         ((Pp[c + 1] - Pp[c]) + (Pm[c + 1] - Pm[c])), D);
                     pbar = 0.5f * (P0[c] + P0[c + 1]);
                     rho_a = 0.5f * (R0[cr] + R0[cr + 1]);
                     kap_a = 0.5f * (K0[cr] + K0[cr + 1]);
                 } else if (ax == 1) {
-                    D = a.g[0] * (P0[c + PW] - P0[c]);
-                    D = fmaf(a.g[1], P0[c + 2 * PW] - P0[c - PW], D);
-                    D = fmaf(a.g[2], P0[c + 3 * PW] - P0[c - 2 * PW], D);
-                    D = fmaf(a.g[3], P0[c + 4 * PW] - P0[c - 3 * PW], D);
-                    D = fmaf(a.g11, ((P0[c + PW + 1] - P0[c + 1]) + (P0[c + PW - 1] - P0[c - 1])) +
+                    const Wts W = weights<PP>(a, PP ? 0.5f * (sc + cell_r2(a, R0[cr + RW], K0[cr + RW])) : 0.0f);
+                    D = W.g0 * (P0[c + PW] - P0[c]);
+                    D = fmaf(W.g1, P0[c + 2 * PW] - P0[c - PW], D);
+                    D = fmaf(W.g2, P0[c + 3 * PW] - P0[c - 2 * PW], D);
+                    D = fmaf(W.g3, P0[c + 4 * PW] - P0[c - 3 * PW], D);
+                    D = fmaf(W.g11, ((P0[c + PW + 1] - P0[c + 1]) + (P0[c + PW - 1] - P0[c - 1])) +
                                         ((Pp[c + PW] - Pp[c]) + (Pm[c + PW] - Pm[c])), D);
                     pbar = 0.5f * (P0[c] + P0[c + PW]);
                     rho_a = 0.5f * (R0[cr] + R0[cr + RW]);
                     kap_a = 0.5f * (K0[cr] + K0[cr + RW]);
                 } else {
-                    D = a.g[0] * (w[4] - w[3]);
-                    D = fmaf(a.g[1], w[5] - w[2], D);
-                    D = fmaf(a.g[2], w[6] - w[1], D);
-                    D = fmaf(a.g[3], w[7] - w[0], D);
-                    D = fmaf(a.g11, ((Pp[c + 1] - P0[c + 1]) + (Pp[c - 1] - P0[c - 1])) +
+                    const Wts W = weights<PP>(a, PP ? 0.5f * (sc + cell_r2(a, Rp[cr], Kp[cr])) : 0.0f);
+                    D = W.g0 * (w[4] - w[3]);
+                    D = fmaf(W.g1, w[5] - w[2], D);
+                    D = fmaf(W.g2, w[6] - w[1], D);
+                    D = fmaf(W.g3, w[7] - w[0], D);
+                    D = fmaf(W.g11, ((Pp[c + 1] - P0[c + 1]) + (Pp[c - 1] - P0[c - 1])) +
                                         ((Pp[c + PW] - P0[c + PW]) + (Pp[c - PW] - P0[c - PW])), D);
                     pbar = 0.5f * (w[3] + w[4]);
                     rho_a = 0.5f * (R0[cr] + Rp[cr]);
@@ -787,7 +829,7 @@ __global__ void check_kernel(const float *p, const Geometry g, float limit, int 
     if (!(fabsf(v) <= limit)) atomicOr(flag, 1);     // also catches NaN
 }
 
-template <int L, bool C, bool PF>
+template <int L, bool C, bool PF, bool PP>
 hipError_t launch_sweep(const StepArgs &a, bool pressure, const KernelConfig &kc, hipStream_t st)
 {
     const int nbx = (a.geo.n[0] + kc.bx - 1) / kc.bx;
@@ -796,9 +838,9 @@ hipError_t launch_sweep(const StepArgs &a, bool pressure, const KernelConfig &kc
 #define FW2_SWEEP(BXV)                                                                                  \
     if (kc.bx == BXV) {                                                                                 \
         if (pressure)                                                                                   \
-            hipLaunchKernelGGL((pressure_sweep2d<L, C, BXV, PF>), dim3(nblocks), dim3(BXV), 0, st, a, kc.rows, nbx, nblocks); \
+            hipLaunchKernelGGL((pressure_sweep2d<L, C, BXV, PF, PP>), dim3(nblocks), dim3(BXV), 0, st, a, kc.rows, nbx, nblocks); \
         else                                                                                            \
-            hipLaunchKernelGGL((velocity_sweep2d<L, C, BXV, PF>), dim3(nblocks), dim3(BXV), 0, st, a, kc.rows, nbx, nblocks); \
+            hipLaunchKernelGGL((velocity_sweep2d<L, C, BXV, PF, PP>), dim3(nblocks), dim3(BXV), 0, st, a, kc.rows, nbx, nblocks); \
         return hipGetLastError();                                                                       \
     }
     FW2_SWEEP(64)
@@ -808,7 +850,7 @@ hipError_t launch_sweep(const StepArgs &a, bool pressure, const KernelConfig &kc
     return hipErrorInvalidValue;
 }
 
-template <int L, bool C>
+template <int L, bool C, bool PP>
 hipError_t launch_sweep3(const StepArgs &a, bool pressure, const KernelConfig &kc, hipStream_t st)
 {
 #define FW2_SWEEP3(BXV, BYV)                                                                            \
@@ -817,10 +859,10 @@ hipError_t launch_sweep3(const StepArgs &a, bool pressure, const KernelConfig &k
         const int nbz = (a.geo.n[2] + kc.rows - 1) / kc.rows;                                           \
         const int nblocks = nbx * nby * nbz;                                                            \
         if (pressure)                                                                                   \
-            hipLaunchKernelGGL((pressure_sweep3d<L, C, BXV, BYV>), dim3(nblocks), dim3(BXV * BYV), 0, st, \
+            hipLaunchKernelGGL((pressure_sweep3d<L, C, BXV, BYV, PP>), dim3(nblocks), dim3(BXV * BYV), 0, st, \
                                a, kc.rows, nbx, nby, nblocks);                                          \
         else                                                                                            \
-            hipLaunchKernelGGL((velocity_sweep3d<L, C, BXV, BYV>), dim3(nblocks), dim3(BXV * BYV), 0, st, \
+            hipLaunchKernelGGL((velocity_sweep3d<L, C, BXV, BYV, PP>), dim3(nblocks), dim3(BXV * BYV), 0, st, \
                                a, kc.rows, nbx, nby, nblocks);                                          \
         return hipGetLastError();                                                                       \
     }
@@ -873,14 +915,14 @@ __global__ void __launch_bounds__(BX) batch_phase(const BatchTable *__restrict__
             float(*sx)[BX + 8] = r0;
             float(*sy)[BX + 2] = r1;
             switch (key) {
-            case 2: pressure_tile2d<1, false, BX, false>(sa, rows, x0, y0, sx, sy); break;
-            case 3: pressure_tile2d<1, true, BX, false>(sa, rows, x0, y0, sx, sy); break;
-            case 4: pressure_tile2d<2, false, BX, false>(sa, rows, x0, y0, sx, sy); break;
-            case 5: pressure_tile2d<2, true, BX, false>(sa, rows, x0, y0, sx, sy); break;
-            case 6: pressure_tile2d<3, false, BX, false>(sa, rows, x0, y0, sx, sy); break;
-            case 7: pressure_tile2d<3, true, BX, false>(sa, rows, x0, y0, sx, sy); break;
-            case 8: pressure_tile2d<4, false, BX, false>(sa, rows, x0, y0, sx, sy); break;
-            case 9: pressure_tile2d<4, true, BX, false>(sa, rows, x0, y0, sx, sy); break;
+            case 2: pressure_tile2d<1, false, BX, false, false>(sa, rows, x0, y0, sx, sy); break;
+            case 3: pressure_tile2d<1, true, BX, false, false>(sa, rows, x0, y0, sx, sy); break;
+            case 4: pressure_tile2d<2, false, BX, false, false>(sa, rows, x0, y0, sx, sy); break;
+            case 5: pressure_tile2d<2, true, BX, false, false>(sa, rows, x0, y0, sx, sy); break;
+            case 6: pressure_tile2d<3, false, BX, false, false>(sa, rows, x0, y0, sx, sy); break;
+            case 7: pressure_tile2d<3, true, BX, false, false>(sa, rows, x0, y0, sx, sy); break;
+            case 8: pressure_tile2d<4, false, BX, false, false>(sa, rows, x0, y0, sx, sy); break;
+            case 9: pressure_tile2d<4, true, BX, false, false>(sa, rows, x0, y0, sx, sy); break;
             default: break;
             }
         } else {
@@ -888,14 +930,14 @@ __global__ void __launch_bounds__(BX) batch_phase(const BatchTable *__restrict__
             float(*sr)[BX + 1] = r2;
             float(*sk)[BX + 1] = reinterpret_cast<float(*)[BX + 1]>(&r1[0][0]);
             switch (key) {
-            case 2: velocity_tile2d<1, false, BX, false>(sa, rows, x0, y0, sp, sr, sk); break;
-            case 3: velocity_tile2d<1, true, BX, false>(sa, rows, x0, y0, sp, sr, sk); break;
-            case 4: velocity_tile2d<2, false, BX, false>(sa, rows, x0, y0, sp, sr, sk); break;
-            case 5: velocity_tile2d<2, true, BX, false>(sa, rows, x0, y0, sp, sr, sk); break;
-            case 6: velocity_tile2d<3, false, BX, false>(sa, rows, x0, y0, sp, sr, sk); break;
-            case 7: velocity_tile2d<3, true, BX, false>(sa, rows, x0, y0, sp, sr, sk); break;
-            case 8: velocity_tile2d<4, false, BX, false>(sa, rows, x0, y0, sp, sr, sk); break;
-            case 9: velocity_tile2d<4, true, BX, false>(sa, rows, x0, y0, sp, sr, sk); break;
+            case 2: velocity_tile2d<1, false, BX, false, false>(sa, rows, x0, y0, sp, sr, sk); break;
+            case 3: velocity_tile2d<1, true, BX, false, false>(sa, rows, x0, y0, sp, sr, sk); break;
+            case 4: velocity_tile2d<2, false, BX, false, false>(sa, rows, x0, y0, sp, sr, sk); break;
+            case 5: velocity_tile2d<2, true, BX, false, false>(sa, rows, x0, y0, sp, sr, sk); break;
+            case 6: velocity_tile2d<3, false, BX, false, false>(sa, rows, x0, y0, sp, sr, sk); break;
+            case 7: velocity_tile2d<3, true, BX, false, false>(sa, rows, x0, y0, sp, sr, sk); break;
+            case 8: velocity_tile2d<4, false, BX, false, false>(sa, rows, x0, y0, sp, sr, sk); break;
+            case 9: velocity_tile2d<4, true, BX, false, false>(sa, rows, x0, y0, sp, sr, sk); break;
             default: break;
             }
         }
@@ -933,38 +975,40 @@ __global__ void __launch_bounds__(256) batch_receivers(const BatchTable *__restr
     if (threadIdx.x == 0) e.rcv.step[0] = step + 1;
 }
 
-template <int NDIM, int L, bool C>
+template <int NDIM, int L, bool C, bool PP>
 hipError_t launch_p(const StepArgs &a, hipStream_t st)
 {
     dim3 block(kBX, kBY);
     dim3 grid((a.geo.n[0] + kBX - 1) / kBX, (a.geo.n[1] + kBY * kRY - 1) / (kBY * kRY), a.geo.n[2]);
-    hipLaunchKernelGGL((pressure_kernel<NDIM, L, C>), grid, block, 0, st, a);
+    hipLaunchKernelGGL((pressure_kernel<NDIM, L, C, PP>), grid, block, 0, st, a);
     return hipGetLastError();
 }
 
-template <int NDIM, int L, bool C>
+template <int NDIM, int L, bool C, bool PP>
 hipError_t launch_v(const StepArgs &a, hipStream_t st)
 {
     dim3 block(kBX, kBY);
     dim3 grid((a.geo.n[0] + kBX - 1) / kBX, (a.geo.n[1] + kBY * kRY - 1) / (kBY * kRY), a.geo.n[2]);
-    hipLaunchKernelGGL((velocity_kernel<NDIM, L, C>), grid, block, 0, st, a);
+    hipLaunchKernelGGL((velocity_kernel<NDIM, L, C, PP>), grid, block, 0, st, a);
     return hipGetLastError();
+}
+
+template <bool P, int NDIM, int L, bool C, bool PP>
+hipError_t dispatch_variant(const StepArgs &a, const KernelConfig &kc, hipStream_t st)
+{
+    if (NDIM == 3 && kc.variant == 1) return launch_sweep3<L, C, PP>(a, P, kc, st);
+    if (NDIM == 2 && kc.variant == 1) return launch_sweep<L, C, false, PP>(a, P, kc, st);
+    if (NDIM == 2 && kc.variant == 2) return launch_sweep<L, C, true, PP>(a, P, kc, st);
+    return P ? launch_p<NDIM, L, C, PP>(a, st) : launch_v<NDIM, L, C, PP>(a, st);
 }
 
 template <bool P, int NDIM, int L>
 hipError_t dispatch_scheme(const StepArgs &a, int scheme, const KernelConfig &kc, hipStream_t st)
 {
-    if (NDIM == 3 && kc.variant == 1) {
-        if (scheme == 0) return launch_sweep3<L, false>(a, P, kc, st);
-        return launch_sweep3<L, true>(a, P, kc, st);
-    }
-    if (NDIM == 2 && (kc.variant == 1 || kc.variant == 2)) {
-        const bool pf = kc.variant == 2;
-        if (scheme == 0) return pf ? launch_sweep<L, false, true>(a, P, kc, st) : launch_sweep<L, false, false>(a, P, kc, st);
-        return pf ? launch_sweep<L, true, true>(a, P, kc, st) : launch_sweep<L, true, false>(a, P, kc, st);
-    }
-    if (scheme == 0) return P ? launch_p<NDIM, L, false>(a, st) : launch_v<NDIM, L, false>(a, st);
-    return P ? launch_p<NDIM, L, true>(a, st) : launch_v<NDIM, L, true>(a, st);
+    const bool pp = a.local_stencil != 0;
+    if (scheme == 0)
+        return pp ? dispatch_variant<P, NDIM, L, false, true>(a, kc, st) : dispatch_variant<P, NDIM, L, false, false>(a, kc, st);
+    return pp ? dispatch_variant<P, NDIM, L, true, true>(a, kc, st) : dispatch_variant<P, NDIM, L, true, false>(a, kc, st);
 }
 
 template <bool P, int NDIM>

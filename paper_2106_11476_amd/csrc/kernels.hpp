@@ -44,6 +44,13 @@ struct StepArgs {
     float g[4];              // g_m0 / h
     float g11;               // g_11 / h
     float dt;
+    // Per-point stencil weights (local_stencil != 0): with s = r^2 of the
+    // point, g_m0(s) / h = sum_k pw[m-1][k] s^k and g_11(s) / h = g11s * s;
+    // a cell's s = q2 / (rho kappa0), q2 = (dt / h)^2.
+    int32_t local_stencil;
+    float pw[4][4];
+    float g11s;
+    float q2;
 };
 
 struct SparseArgs {

@@ -6,13 +6,15 @@
 
 namespace fw2 {
 
-void stencil_weights(double r, int ndim, double g[4], double *g11)
+namespace {
+
+// Solve the axial Taylor conditions sum_j (2j-1)^(2k-1) c_j = rhs[k] (k = 1..4).
+void solve_axial(const double rhs[4], double c[4])
 {
-    // Augmented 4x5 system, row k: sum_j (2j-1)^(2k-1) c_j = r^(2k-2).
     double A[4][5];
     for (int k = 0; k < 4; ++k) {
         for (int j = 0; j < 4; ++j) A[k][j] = std::pow(2.0 * j + 1.0, 2.0 * k + 1.0);
-        A[k][4] = std::pow(r, 2.0 * k);
+        A[k][4] = rhs[k];
     }
     for (int col = 0; col < 4; ++col) {          // Gaussian elimination, partial pivoting
         int piv = col;
@@ -25,15 +27,39 @@ void stencil_weights(double r, int ndim, double g[4], double *g11)
             for (int j = col; j < 5; ++j) A[row][j] -= f * A[col][j];
         }
     }
-    double c[4];
     for (int row = 3; row >= 0; --row) {
         double s = A[row][4];
         for (int j = row + 1; j < 4; ++j) s -= A[row][j] * c[j];
         c[row] = s / A[row][row];
     }
+}
+
+}  // namespace
+
+void stencil_weights(double r, int ndim, double g[4], double *g11)
+{
+    // right-hand side r^(2k-2)
+    double rhs[4], c[4];
+    for (int k = 0; k < 4; ++k) rhs[k] = std::pow(r, 2.0 * k);
+    solve_axial(rhs, c);
     *g11 = r * r / 24.0;
     for (int j = 0; j < 4; ++j) g[j] = c[j];
     g[0] = c[0] - 2.0 * (ndim - 1) * (*g11);
+}
+
+void stencil_polynomials(int ndim, double pw[4][4], double *g11_per_s)
+{
+    // The weights are linear in the right-hand side (1, s, s^2, s^3), s = r^2:
+    // column k of the solution for the unit right-hand side e_k is the s^k
+    // coefficient.  g_10 carries the cross-term correction -2(d-1) s / 24.
+    for (int k = 0; k < 4; ++k) {
+        double e[4] = {0.0, 0.0, 0.0, 0.0}, c[4];
+        e[k] = 1.0;
+        solve_axial(e, c);
+        for (int j = 0; j < 4; ++j) pw[j][k] = c[j];
+    }
+    pw[0][1] -= 2.0 * (ndim - 1) / 24.0;
+    *g11_per_s = 1.0 / 24.0;
 }
 
 double stability_factor(double r, int ndim, const double g[4], double g11)

@@ -13,6 +13,10 @@ namespace fw2 {
 // on-axis weight gives up 2 (ndim-1) g11 to the cross terms.
 void stencil_weights(double r, int ndim, double g[4], double *g11);
 
+// The same weights as polynomials in s = r^2: g_m0(s) = sum_k pw[m-1][k] s^k,
+// g_11(s) = g11_per_s * s.
+void stencil_polynomials(int ndim, double pw[4][4], double *g11_per_s);
+
 // Largest |sin(w dt / 2)| of the leapfrog with these weights over the
 // Brillouin zone; the scheme is stable when it is below 1.
 double stability_factor(double r, int ndim, const double g[4], double g11);

@@ -18,6 +18,7 @@ STATUS = {0: "FW2_OK", 1: "FW2_E_INVALID", 2: "FW2_E_NOMEM", 3: "FW2_E_HIP", 4: 
 FIELD_P, FIELD_V, FIELD_PSI1, FIELD_PSI2, FIELD_ALL = 1, 2, 4, 8, 15
 HOST, DEVICE = 0, 1
 RELAX_PRINTED, RELAX_CENTRED = 0, 1
+STENCIL_GLOBAL, STENCIL_LOCAL = 0, 1
 
 EXPORTS = ["fw2_workspace_bytes", "fw2_create_domain", "fw2_add_source", "fw2_add_receivers",
            "fw2_step", "fw2_read_fields", "fw2_write_fields", "fw2_current_step",
@@ -41,7 +42,7 @@ class DomainDesc(ctypes.Structure):
         ("h", ctypes.c_double), ("dt", ctypes.c_double),
         ("bound_cells", ctypes.c_int32 * 3), ("trans_cells", ctypes.c_int32 * 3),
         ("pml_Rc", ctypes.c_double), ("pml_npoly", ctypes.c_int32), ("pml_cp", ctypes.c_double),
-        ("fd_r", ctypes.c_double), ("relax_scheme", ctypes.c_int32),
+        ("fd_r", ctypes.c_double), ("relax_scheme", ctypes.c_int32), ("stencil_mode", ctypes.c_int32),
         ("c", ctypes.c_void_p), ("rho", ctypes.c_void_p), ("beta", ctypes.c_void_p),
         ("label", ctypes.c_void_p), ("n_labels", ctypes.c_int32), ("relax_table", ctypes.c_void_p),
         ("stream", ctypes.c_void_p),
@@ -131,6 +132,7 @@ def make_desc(prob, stream=None):
     d.pml_Rc, d.pml_npoly, d.pml_cp = float(prob.pml_Rc), int(prob.pml_npoly), float(prob.pml_cp or 0.0)
     d.fd_r = float(prob.fd_r or 0.0)
     d.relax_scheme = int(getattr(prob, "relax_scheme", RELAX_CENTRED))
+    d.stencil_mode = int(getattr(prob, "stencil_mode", STENCIL_GLOBAL))
     d.c = host(prob.c, np.float32)
     d.rho = host(prob.rho, np.float32)
     d.beta = host(prob.beta, np.float32)
