@@ -194,6 +194,11 @@ fw2_status fw2_check_finite(fw2_domain *dom, float limit);
  *   fw2_adjoint_step: reverse of forward step `step`, given the saved state
  *     block at that step's input and the device residual trace[step] - obs[step]
  *     ([n_rcv] FP32, or NULL for no residual).  Call for step = n-1 down to 0.
+ *     dev_state_prev, if not NULL, is the state block at the input of step - 1:
+ *     the library then recomputes that step's pressure phase in the same pass
+ *     (the next call must be for step - 1; otherwise that work is redone).
+ *     The buffers dev_state and dev_state_prev must stay unchanged until the
+ *     work queued on the domain's stream has run.
  *   fw2_adjoint_gradient: dJ/dc, packed FP32 [nz][ny][nx] into dst (host or
  *     device); synchronises. */
 fw2_status fw2_state_bytes(const fw2_domain *dom, uint64_t *bytes);
@@ -201,7 +206,8 @@ fw2_status fw2_save_state(fw2_domain *dom, void *dev_dst);
 fw2_status fw2_load_state(fw2_domain *dom, const void *dev_src, int64_t step);
 fw2_status fw2_adjoint_workspace_bytes(const fw2_domain *dom, uint64_t *bytes);
 fw2_status fw2_adjoint_begin(fw2_domain *dom, void *dev_workspace, uint64_t workspace_bytes);
-fw2_status fw2_adjoint_step(fw2_domain *dom, const void *dev_state, int64_t step, const float *dev_residual);
+fw2_status fw2_adjoint_step(fw2_domain *dom, const void *dev_state, const void *dev_state_prev, int64_t step,
+                            const float *dev_residual);
 fw2_status fw2_adjoint_gradient(fw2_domain *dom, float *dst, int32_t dst_kind);
 
 /* ---- Batched stepping of many 2D domains (continuous batching) ----------

@@ -94,7 +94,8 @@ def _misfit_function():
                     if i + 1 < m:
                         dom.step(1)
                 for k in reversed(range(m)):
-                    dom.adjoint_step(seg[k], n0 + k, None if res is None else res[n0 + k])
+                    dom.adjoint_step(seg[k], n0 + k, None if res is None else res[n0 + k],
+                                     prev=seg[k - 1] if k > 0 else None)
             g = dom.adjoint_gradient()
             shape, dtype, device = ctx.c_meta
             grad = g.reshape(shape).to(device=device, dtype=dtype)

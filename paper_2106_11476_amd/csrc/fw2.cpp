@@ -186,6 +186,7 @@ struct fw2_domain {
     int64_t count[2] = {0, 0};
     bool adjoint = false;
     fw2::AdjointBuffers adj;
+    int64_t adj_pp_step = -1;        // step whose p'' and S the adjoint buffers hold
     int64_t npts() const { return (int64_t)ly.geo.n[0] * ly.geo.n[1] * ly.geo.n[2]; }
 };
 
@@ -731,16 +732,23 @@ fw2_status fw2_adjoint_begin(fw2_domain *d, void *dev_workspace, uint64_t bytes)
     b.out = b.gk + S;
     FW2_HIP(hipMemsetAsync(dev_workspace, 0, need, d->stream));
     d->adjoint = true;
+    d->adj_pp_step = -1;
     return FW2_OK;
 }
 
-fw2_status fw2_adjoint_step(fw2_domain *d, const void *dev_state, int64_t step, const float *dev_residual)
+fw2_status fw2_adjoint_step(fw2_domain *d, const void *dev_state, const void *dev_state_prev, int64_t step,
+                            const float *dev_residual)
 {
     if (!d) return fail(FW2_E_STATE, "domain is NULL");
     if (!d->adjoint) return fail(FW2_E_STATE, "fw2_adjoint_begin first");
     if (!dev_state || step < 0) return fail(FW2_E_INVALID, "state is NULL or step < 0");
-    FW2_HIP(fw2::launch_adjoint_step(d->args, d->src, d->rcv, d->desc.n_relax, (const float *)dev_state, d->adj, step,
-                                     dev_residual, d->stream));
+    bool next = false;
+    const hipError_t e = fw2::launch_adjoint_step(d->args, d->src, d->rcv, d->desc.n_relax, (const float *)dev_state,
+                                                  (const float *)dev_state_prev, d->adj, step,
+                                                  d->adj_pp_step == step, dev_residual, d->stream, &next);
+    d->adj_pp_step = -1;
+    FW2_HIP(e);
+    if (next) d->adj_pp_step = step - 1;
     return FW2_OK;
 }
 

@@ -112,9 +112,14 @@ hipError_t launch_batch_step(const BatchTable *dev_table, int n_entries_max, int
 struct AdjointBuffers {
     float *lp, *pp, *sS, *lDv, *lpb, *lkv, *lDp, *gk, *out;
 };
+// One reverse step.  state: forward state block at the step's input;
+// state_prev: that of the step before, or nullptr.  have_pp: b.pp / b.sS
+// already hold this step's p'' and S (from the previous call); *pp_next is
+// set when they now hold those of step - 1.
 hipError_t launch_adjoint_step(const StepArgs &f, const SparseArgs &src, const SparseArgs &rcv, int L,
-                               const float *state, const AdjointBuffers &b, long long step,
-                               const float *residual, hipStream_t stream);
+                               const float *state, const float *state_prev, const AdjointBuffers &b,
+                               long long step, bool have_pp, const float *residual, hipStream_t stream,
+                               bool *pp_next);
 hipError_t launch_adjoint_gradient(const StepArgs &f, const AdjointBuffers &b, hipStream_t stream);
 
 // Launchers (kernels.hip).  All enqueue on `stream` and return the launch error.

@@ -83,7 +83,7 @@ def lib():
             "fw2_load_state": [vp, vp, i64],
             "fw2_adjoint_workspace_bytes": [vp, ctypes.POINTER(u64)],
             "fw2_adjoint_begin": [vp, vp, u64],
-            "fw2_adjoint_step": [vp, vp, i64, vp],
+            "fw2_adjoint_step": [vp, vp, vp, i64, vp],
             "fw2_adjoint_gradient": [vp, vp, i32],
         }
         for name, args in sig.items():
@@ -259,9 +259,12 @@ class Domain:
         self.torch.cuda.synchronize(self.device)
         _check(lib().fw2_adjoint_begin(self._h, ctypes.c_void_p(self._adj_ws.data_ptr()), int(n.value)))
 
-    def adjoint_step(self, state, step, residual=None):
+    def adjoint_step(self, state, step, residual=None, prev=None):
+        """Reverse of step `step` from its input state; prev: the input state
+        of step - 1 if at hand (lets the library fuse its recompute)."""
         r = ctypes.c_void_p(residual.data_ptr()) if residual is not None else None
-        _check(lib().fw2_adjoint_step(self._h, ctypes.c_void_p(state.data_ptr()), int(step), r))
+        q = ctypes.c_void_p(prev.data_ptr()) if prev is not None else None
+        _check(lib().fw2_adjoint_step(self._h, ctypes.c_void_p(state.data_ptr()), q, int(step), r))
 
     def adjoint_gradient(self):
         """dJ/dc as a device tensor of the grid's shape ([nz][ny][nx])."""
