@@ -250,7 +250,7 @@ def adjoint_leg(steps=6000, K=64, shot=31, timed_reverse=200):
     dom.adjoint_begin()
     # steady state of the backward sweep: consecutive steps, each call handed
     # the state of the step before (the same block stands in for every state)
-    s0 = steps - 1
+    s0 = max(steps - 1, 20 + timed_reverse)
     for k in range(20):
         dom.adjoint_step(st, s0 - k, res[0], prev=st)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -282,6 +282,18 @@ def _db_rows(db, sql):
         return list(con.execute(sql))
     finally:
         con.close()
+
+
+def summarize_stats_only(stats_db, name, title, commands):
+    """Write profiles/kernel_stats_<name>.txt from a kernel-trace database."""
+    stats = _db_rows(stats_db, "select name, total_calls, total_duration, average from top_kernels")
+    lines = ["rocprofv3 kernel statistics: %s" % title, "commands:"] + ["  " + c for c in commands]
+    lines.append("kernel_source_sha256_16: %s" % kernel_source_sha())
+    lines.append("%-70s %8s %12s %10s" % ("kernel", "calls", "total_us", "avg_us"))
+    for kname, calls, tot, avg in stats:
+        lines.append("%-70s %8d %12.1f %10.3f" % (kname[:70], calls, tot, avg))
+    with open(os.path.join(PROFILES, "kernel_stats_%s.txt" % name), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
 
 
 def summarize_profiles(stats_db, fetch_db, write_db, workload, copy_bytes, commands):
@@ -366,7 +378,12 @@ def main():
     ap.add_argument("--copy-read-bytes", type=int, default=256 * (1 << 20),
                     help="bytes the probe copy reads (and writes) per dispatch")
     ap.add_argument("--commands", nargs="*", default=[])
+    ap.add_argument("--summarize-stats", nargs=3, metavar=("STATS_DB", "NAME", "TITLE"),
+                    help="write profiles/kernel_stats_NAME.txt from one kernel-trace database and exit")
     args = ap.parse_args()
+    if args.summarize_stats:
+        summarize_stats_only(*args.summarize_stats, commands=args.commands)
+        return
     if args.summarize:
         summarize_profiles(*args.summarize, workload=args.workload, copy_bytes=args.copy_read_bytes,
                            commands=args.commands)
