@@ -174,7 +174,9 @@ class Domain:
         self.workspace_bytes = int(nbytes.value)
         with torch.cuda.device(self.device):
             self.workspace = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self.device)
-        torch.cuda.synchronize(self.device)
+        # inputs prepared on the current stream are complete before the library
+        # uses them on its own stream (other streams keep running)
+        torch.cuda.current_stream(self.device).synchronize()
         h = ctypes.c_void_p()
         _check(lib().fw2_create_domain(ctypes.byref(d), ctypes.c_void_p(self.workspace.data_ptr()),
                                        self.workspace_bytes, ctypes.byref(h)))
@@ -194,7 +196,7 @@ class Domain:
         if s.ndim == 1:
             s = s[None, :]
         sg = t.as_tensor(np.ascontiguousarray(s), device=self.device).contiguous()
-        t.cuda.synchronize(self.device)
+        t.cuda.current_stream(self.device).synchronize()
         _check(lib().fw2_add_source(self._h, int(idx.numel()), ctypes.c_void_p(idx.data_ptr()),
                                     ctypes.c_void_p(sig.data_ptr()), ctypes.c_void_p(w.data_ptr()),
                                     int(sg.shape[0]), int(sg.shape[1]), ctypes.c_void_p(sg.data_ptr())))
@@ -205,7 +207,7 @@ class Domain:
         idx = t.as_tensor(np.asarray(flat_idx, np.int64), device=self.device).contiguous()
         n = int(idx.numel())
         trace = t.zeros((int(cap_steps), max(n, 1)), dtype=t.float32, device=self.device)
-        t.cuda.synchronize(self.device)
+        t.cuda.current_stream(self.device).synchronize()
         _check(lib().fw2_add_receivers(self._h, n, ctypes.c_void_p(idx.data_ptr()),
                                        ctypes.c_void_p(trace.data_ptr()), int(cap_steps)))
         self._rcv = idx

@@ -81,6 +81,12 @@ class Server:
     budget_bytes -- device memory the resident requests may hold together
     max_active   -- largest number of requests advanced by one launch (<= 64)
     chunk        -- steps between admission / completion points
+
+    Host work overlaps device work: while a chunk of steps runs on the batch
+    stream, arrived requests are admitted (arrival order, memory budget and
+    slots counted over running and staged requests) and their domains are
+    built on a separate setup stream; they join the batch at the next chunk
+    boundary, when finished requests also hand back their traces.
     """
 
     def __init__(self, budget_bytes, max_active=32, chunk=64, device="cuda:0", tile=(256, 4)):
@@ -91,11 +97,12 @@ class Server:
         self.max_active = int(max_active)
         self.chunk = int(chunk)
         self.stream = torch.cuda.Stream(device=self.device)
+        self.setup_stream = torch.cuda.Stream(device=self.device)
         self.batch = fw2.Batch(max_domains=self.max_active, device=self.device, stream=self.stream)
         self.batch.set_tile(*tile)
 
     def _start(self, r):
-        dom = fw2.Domain(r.problem, device=self.device, stream=self.stream)
+        dom = fw2.Domain(r.problem, device=self.device, stream=self.setup_stream)
         if len(r.problem.src_idx):
             dom.add_source(r.problem.src_idx, r.problem.src_sig, r.problem.src_w, r.problem.signals)
         dom.add_receivers(r.problem.rcv_idx, r.n_steps)
@@ -108,23 +115,49 @@ class Server:
             r.footprint = footprint_bytes(r.problem, r.n_steps)
             if r.footprint > self.budget:
                 raise ValueError("request %d needs %d bytes, above the budget" % (r.rid, r.footprint))
-        active = []               # (request, domain)
+        active = []               # (request, domain) in the batch
+        staged = []               # (request, domain) built, joining at the next boundary
+        in_flight = False         # a chunk is queued on the batch stream
         stats = Stats()
         t0 = clock()
-        while queue or active:
+        while queue or active or staged:
+            # admit and build while the chunk in flight runs
             now = clock() - t0
-            used = sum(r.footprint for r, _ in active)
-            new = admit(queue, used, self.budget, self.max_active - len(active), now)
+            held = active + staged
+            new = admit(queue, sum(r.footprint for r, _ in held), self.budget,
+                        self.max_active - len(held), now)
             for r in new:
                 queue.remove(r)
                 r.admitted = clock() - t0
-                active.append((r, self._start(r)))
-            if new:
+                staged.append((r, self._start(r)))
+            changed = False
+            finished = []
+            if in_flight:
+                self.stream.synchronize()
+                in_flight = False
+                finished = [(r, d) for r, d in active if d.current_step() >= r.n_steps]
+                if finished:
+                    active = [(r, d) for r, d in active if d.current_step() < r.n_steps]
+                    changed = True
+                    for r, d in finished:
+                        r.trace = d.trace.cpu().numpy()
+                        r.done = clock() - t0
+                        stats.latencies.append(r.done - r.arrival)
+                        stats.completed += 1
+            if staged:
+                active += staged
+                staged = []
+                changed = True
+            if changed:
+                # the batch table stops referring to finished domains before they go
                 self.batch.set_domains([d for _, d in active], [r.n_steps for r, _ in active])
+                for _, d in finished:
+                    d.destroy_domain()
             if not active:
-                wait = queue[0].arrival - (clock() - t0)
-                if wait > 0:
-                    time.sleep(min(wait, 0.05))
+                if queue:
+                    wait = queue[0].arrival - (clock() - t0)
+                    if wait > 0:
+                        time.sleep(min(wait, 0.05))
                 continue
             stats.peak_bytes = max(stats.peak_bytes, sum(r.footprint for r, _ in active))
             stats.peak_active = max(stats.peak_active, len(active))
@@ -133,18 +166,7 @@ class Server:
             to_done = min(r.n_steps - d.current_step() for r, d in active)
             k = to_done if (not queue or len(active) >= self.max_active) else min(to_done, self.chunk)
             self.batch.step(max(int(k), 1))
-            self.stream.synchronize()
-            finished = [(r, d) for r, d in active if d.current_step() >= r.n_steps]
-            if finished:
-                keep = [(r, d) for r, d in active if d.current_step() < r.n_steps]
-                self.batch.set_domains([d for _, d in keep], [r.n_steps for r, _ in keep])
-                for r, d in finished:
-                    r.trace = d.trace.cpu().numpy()
-                    r.done = clock() - t0
-                    stats.latencies.append(r.done - r.arrival)
-                    stats.completed += 1
-                    d.destroy_domain()
-                active = keep
+            in_flight = True
         stats.makespan = clock() - t0
         return stats
 
