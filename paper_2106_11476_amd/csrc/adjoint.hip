@@ -45,7 +45,6 @@ struct AdjArgs {
     float *lkv;              // [ndim] adjoint of kappa0_a
     float *lDp;              // [ndim] adjoint of D^- v_a at p points
     float *gk;               // dJ/dkappa0
-    int L;
 };
 
 __device__ __forceinline__ int64_t aoff(const Geometry &g, int a)
@@ -97,27 +96,27 @@ __device__ __forceinline__ int slot_v(int x, int n, int nb) { return max(max(nb 
     const int k = blockIdx.z;                                                      \
     if (i >= g.n[0] || j >= g.n[1]) return;                                        \
     const int c3[3] = {i, j, k};                                                   \
-    const int nd = g.ndim;                                                         \
     const int64_t idx = g.origin + (int64_t)k * g.plane + (int64_t)j * g.pitch + i; \
     const int lab = A.f.label ? (int)A.f.label[idx] : 0;                           \
-    const int L = A.L;                                                             \
     (void)c3;                                                                      \
-    (void)lab;                                                                     \
-    (void)nd;                                                                      \
-    (void)L;
+    (void)lab;
 
 // A0: forward recompute of the pressure phase (without sources).
+template <int ND, int L>
 __global__ void __launch_bounds__(kABX *kABY) adj_forward_p(const AdjArgs A)
 {
+    constexpr int nd = ND;
     ADJ_POINT
     const int64_t st = g.stride;
     const float *v = A.sp + st;
     const float *m2 = A.sp + (int64_t)(1 + nd + nd * L) * st;
     float S = 0.0f;
+#pragma unroll
     for (int a = 0; a < nd; ++a) {
         const float D = dminus(v + a * st, g, A.f.g, A.f.g11, a, nd, idx);
         const int t = slot_p(c3[a], g.n[a], A.f.nb[a]) * A.f.n_labels + lab;
         float Sa = A.f.w2[a][t] * D;
+#pragma unroll
         for (int nu = 0; nu < L; ++nu) Sa += m2[(int64_t)(a * L + nu) * st + idx];
         S += Sa;
     }
@@ -143,13 +142,16 @@ __global__ void adj_sources(float *pp, const SparseArgs s, long long step)
 }
 
 // A1: velocity phase reversed at v points.
+template <int ND, int L>
 __global__ void __launch_bounds__(kABX *kABY) adj_velocity(const AdjArgs A)
 {
+    constexpr int nd = ND;
     ADJ_POINT
     const int64_t st = g.stride;
     const float *m1 = A.sp + (int64_t)(1 + nd) * st;
     float *lv = A.lp + st;
     float *lm1 = A.lp + (int64_t)(1 + nd) * st;
+#pragma unroll
     for (int a = 0; a < nd; ++a) {
         float *oDv = A.lDv + a * st, *opb = A.lpb + a * st, *okv = A.lkv + a * st;
         if (c3[a] == g.n[a] - 1) {                       // outside the grid: no adjoint flow
@@ -164,6 +166,7 @@ __global__ void __launch_bounds__(kABX *kABY) adj_velocity(const AdjArgs A)
         const float2 *bc = A.f.bc1[a] + (int64_t)t * L;
         const float w = A.f.w1[a][t];
         float Sv = w * D;
+#pragma unroll
         for (int nu = 0; nu < L; ++nu) Sv += m1[(int64_t)(a * L + nu) * st + idx];
         const float pbar = 0.5f * (A.pp[idx] + A.pp[idx + o]);
         const float rho_a = 0.5f * (A.f.rho[idx] + A.f.rho[idx + o]);
@@ -173,6 +176,7 @@ __global__ void __launch_bounds__(kABX *kABY) adj_velocity(const AdjArgs A)
         const float lS = -A.f.dt * lva / Q;
         const float lQ = A.f.dt * Sv * lva / (Q * Q);
         float lD = w * lS;
+#pragma unroll
         for (int nu = 0; nu < L; ++nu) {
             const int64_t c = (int64_t)(a * L + nu) * st + idx;
             const float2 q = bc[nu];
@@ -194,12 +198,15 @@ __global__ void adj_receivers(float *lp, const SparseArgs r, const float *__rest
 }
 
 // A2: gather of the velocity-phase adjoints, then the pressure phase reversed.
+template <int ND, int L>
 __global__ void __launch_bounds__(kABX *kABY) adj_pressure(const AdjArgs A)
 {
+    constexpr int nd = ND;
     ADJ_POINT
     const int64_t st = g.stride;
     float lpp = A.lp[idx];
     float gk = A.gk[idx];
+#pragma unroll
     for (int a = 0; a < nd; ++a) {
         const int64_t o = aoff(g, a);
         lpp -= dminus(A.lDv + a * st, g, A.f.g, A.f.g11, a, nd, idx);
@@ -215,10 +222,12 @@ __global__ void __launch_bounds__(kABX *kABY) adj_pressure(const AdjArgs A)
     A.lp[idx] = lpp + lK * x * q;
     A.gk[idx] = gk + lK * (1.0f + 2.0f * q * p0);
     float *lm2 = A.lp + (int64_t)(1 + nd + nd * L) * st;
+#pragma unroll
     for (int a = 0; a < nd; ++a) {
         const int t = slot_p(c3[a], g.n[a], A.f.nb[a]) * A.f.n_labels + lab;
         const float2 *bc = A.f.bc2[a] + (int64_t)t * L;
         float lD = A.f.w2[a][t] * lS;
+#pragma unroll
         for (int nu = 0; nu < L; ++nu) {
             const int64_t c = (int64_t)(a * L + nu) * st + idx;
             const float2 qq = bc[nu];
@@ -231,11 +240,14 @@ __global__ void __launch_bounds__(kABX *kABY) adj_pressure(const AdjArgs A)
 }
 
 // A3: lam_v_a -= D^+(lam_D_a) at v points inside the grid.
+template <int ND, int L>
 __global__ void __launch_bounds__(kABX *kABY) adj_vel_from_p(const AdjArgs A)
 {
+    constexpr int nd = ND;
     ADJ_POINT
     const int64_t st = g.stride;
     float *lv = A.lp + st;
+#pragma unroll
     for (int a = 0; a < nd; ++a) {
         if (c3[a] == g.n[a] - 1) continue;
         lv[a * st + idx] -= dplus(A.lDp + a * st, g, A.f.g, A.f.g11, a, nd, idx);
@@ -384,7 +396,8 @@ __global__ void __launch_bounds__(BX) adj_v_sweep2d(const AdjSweep A)
 #pragma unroll
             for (int ax = 0; ax < 2; ++ax)
 #pragma unroll
-                for (int nu = 0; nu < L; ++nu) {
+        #pragma unroll
+        for (int nu = 0; nu < L; ++nu) {
                     m[ax][nu] = m1[(int64_t)(ax * L + nu) * st + idx];
                     lm[ax][nu] = lm1[(int64_t)(ax * L + nu) * st + idx];
                 }
@@ -443,7 +456,8 @@ __global__ void __launch_bounds__(BX) adj_v_sweep2d(const AdjSweep A)
                 const float lQ = a.dt * Sv * lvx / (Q * Q);
                 float lD = w * lS;
 #pragma unroll
-                for (int nu = 0; nu < L; ++nu) {
+        #pragma unroll
+        for (int nu = 0; nu < L; ++nu) {
                     const float2 q = bc[nu];
                     lD = fmaf(q.y, lm[0][nu], lD);
                     lm[0][nu] = fmaf(q.x, lm[0][nu], lS);
@@ -483,7 +497,8 @@ __global__ void __launch_bounds__(BX) adj_v_sweep2d(const AdjSweep A)
                 const float lQ = a.dt * Sv * lvy / (Q * Q);
                 float lD = w * lS;
 #pragma unroll
-                for (int nu = 0; nu < L; ++nu) {
+        #pragma unroll
+        for (int nu = 0; nu < L; ++nu) {
                     const float2 q = bc[nu];
                     lD = fmaf(q.y, lm[1][nu], lD);
                     lm[1][nu] = fmaf(q.x, lm[1][nu], lS);
@@ -648,7 +663,8 @@ __global__ void __launch_bounds__(BX) adj_p_sweep2d(const AdjSweep A)
                     const float2 *__restrict__ bc = a.bc2[ax] + (int64_t)tt * L;
                     float lD = a.w2[ax][tt] * lS;
 #pragma unroll
-                    for (int nu = 0; nu < L; ++nu) {
+            #pragma unroll
+        for (int nu = 0; nu < L; ++nu) {
                         const int64_t c = (int64_t)(ax * L + nu) * st + idx;
                         const float2 q = bc[nu];
                         const float lmn = lm2[c];
@@ -738,6 +754,41 @@ hipError_t adjoint_step_2d(AdjSweep A, const SparseArgs &src, const float *state
 }  // namespace
 #endif  // FW2_ADJOINT_SWEEPS
 
+namespace {
+
+// one thread per point, the four phases in turn
+template <int ND, int L>
+hipError_t adjoint_step_points(const StepArgs &f, const SparseArgs &src, const SparseArgs &rcv, const float *state,
+                               const AdjointBuffers &b, long long step, const float *residual, hipStream_t st,
+                               bool *pp_next)
+{
+    AdjArgs A;
+    A.f = f;
+    A.sp = state;
+    A.lp = b.lp;
+    A.pp = b.pp;
+    A.sS = b.sS;
+    A.lDv = b.lDv;
+    A.lpb = b.lpb;
+    A.lkv = b.lkv;
+    A.lDp = b.lDp;
+    A.gk = b.gk;
+    const Geometry &g = f.geo;
+    dim3 block(kABX, kABY), grid((g.n[0] + kABX - 1) / kABX, (g.n[1] + kABY - 1) / kABY, g.n[2]);
+    hipLaunchKernelGGL((adj_forward_p<ND, L>), grid, block, 0, st, A);
+    if (src.n > 0 && step < src.n_t)
+        hipLaunchKernelGGL(adj_sources, dim3((src.n + 255) / 256), dim3(256), 0, st, b.pp, src, step);
+    hipLaunchKernelGGL((adj_velocity<ND, L>), grid, block, 0, st, A);
+    if (rcv.n > 0 && residual)
+        hipLaunchKernelGGL(adj_receivers, dim3((rcv.n + 255) / 256), dim3(256), 0, st, b.lp, rcv, residual);
+    hipLaunchKernelGGL((adj_pressure<ND, L>), grid, block, 0, st, A);
+    hipLaunchKernelGGL((adj_vel_from_p<ND, L>), grid, block, 0, st, A);
+    *pp_next = false;
+    return hipGetLastError();
+}
+
+}  // namespace
+
 hipError_t launch_adjoint_step(const StepArgs &f, const SparseArgs &src, const SparseArgs &rcv, int L,
                                const float *state, const float *state_prev, const AdjointBuffers &b,
                                long long step, bool have_pp, const float *residual, hipStream_t st,
@@ -768,32 +819,19 @@ hipError_t launch_adjoint_step(const StepArgs &f, const SparseArgs &src, const S
     (void)state_prev;
     (void)have_pp;
 #endif
-    // one thread per point, the four phases in turn
-    AdjArgs A;
-    A.f = f;
-    A.sp = state;
-    A.lp = b.lp;
-    A.pp = b.pp;
-    A.sS = b.sS;
-    A.lDv = b.lDv;
-    A.lpb = b.lpb;
-    A.lkv = b.lkv;
-    A.lDp = b.lDp;
-    A.gk = b.gk;
-    A.L = L;
-    const Geometry &g = f.geo;
-    dim3 block(kABX, kABY), grid((g.n[0] + kABX - 1) / kABX, (g.n[1] + kABY - 1) / kABY, g.n[2]);
-    hipLaunchKernelGGL(adj_forward_p, grid, block, 0, st, A);
-    if (src.n > 0)
-        hipLaunchKernelGGL(adj_sources, dim3((src.n + 255) / 256), dim3(256), 0, st, b.pp, src, step);
-    hipLaunchKernelGGL(adj_velocity, grid, block, 0, st, A);
-    if (rcv.n > 0 && residual)
-        hipLaunchKernelGGL(adj_receivers, dim3((rcv.n + 255) / 256), dim3(256), 0, st, b.lp, rcv, residual);
-    hipLaunchKernelGGL(adj_pressure, grid, block, 0, st, A);
-    hipLaunchKernelGGL(adj_vel_from_p, grid, block, 0, st, A);
-    *pp_next = false;
-    return hipGetLastError();
+    switch (f.geo.ndim * 8 + L) {
+    case 2 * 8 + 1: return adjoint_step_points<2, 1>(f, src, rcv, state, b, step, residual, st, pp_next);
+    case 2 * 8 + 2: return adjoint_step_points<2, 2>(f, src, rcv, state, b, step, residual, st, pp_next);
+    case 2 * 8 + 3: return adjoint_step_points<2, 3>(f, src, rcv, state, b, step, residual, st, pp_next);
+    case 2 * 8 + 4: return adjoint_step_points<2, 4>(f, src, rcv, state, b, step, residual, st, pp_next);
+    case 3 * 8 + 1: return adjoint_step_points<3, 1>(f, src, rcv, state, b, step, residual, st, pp_next);
+    case 3 * 8 + 2: return adjoint_step_points<3, 2>(f, src, rcv, state, b, step, residual, st, pp_next);
+    case 3 * 8 + 3: return adjoint_step_points<3, 3>(f, src, rcv, state, b, step, residual, st, pp_next);
+    case 3 * 8 + 4: return adjoint_step_points<3, 4>(f, src, rcv, state, b, step, residual, st, pp_next);
+    default: return hipErrorInvalidValue;
+    }
 }
+
 
 hipError_t launch_adjoint_gradient(const StepArgs &f, const AdjointBuffers &b, hipStream_t st)
 {
