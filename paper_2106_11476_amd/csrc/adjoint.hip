@@ -20,10 +20,11 @@
 //       lam_D_a = w2 lam_S + sum c2 lam_psi2 (new)
 //   A3  v points inside the grid: lam_v_a -= D^+(lam_D_a)
 // using (D^-)^T = -(D^+) and (D^+)^T = -(D^-).
-// The four phases run as one-thread-per-point kernels.  A 2D variant as two
-// row sweeps per step (A3 deferred into the next step's velocity sweep, the
-// next step's A0 fused into this step's pressure sweep) is kept below behind
-// a compile-time switch.
+// The phases run as one-thread-per-point kernels, two per step: A3 of a step
+// is deferred into the velocity kernel (A1) of the next call, and A0 of the
+// step before is fused into the pressure kernel (A2) when its state is at
+// hand.  A 2D variant as two row sweeps per step is kept below behind a
+// compile-time switch.
 #include "kernels.hpp"
 
 #include <cstring>
@@ -37,6 +38,7 @@ constexpr int kABX = 64, kABY = 4;
 struct AdjArgs {
     StepArgs f;              // medium, tables, stencil of the domain (f.p etc. unused)
     const float *sp;         // forward state at the step input: p, v, psi1, psi2 blocks
+    const float *sq;         // forward state of the step before (A0 fused into A2), or unused
     float *lp;               // adjoint state: same layout
     float *pp;               // p'' (forward recompute)
     float *sS;               // S of the pressure phase (forward recompute)
@@ -141,8 +143,9 @@ __global__ void adj_sources(float *pp, const SparseArgs s, long long step)
     pp[pi] = pp[pi] + s.w[q] * s.signals[(int64_t)s.sig[q] * s.n_t + step];
 }
 
-// A1: velocity phase reversed at v points.
-template <int ND, int L>
+// A1: velocity phase reversed at v points.  DEFER_A3: first apply the A3 of
+// the step after (lam_v -= D^+ lam_Dp, lam_Dp left by the previous call).
+template <int ND, int L, bool DEFER_A3>
 __global__ void __launch_bounds__(kABX *kABY) adj_velocity(const AdjArgs A)
 {
     constexpr int nd = ND;
@@ -172,7 +175,11 @@ __global__ void __launch_bounds__(kABX *kABY) adj_velocity(const AdjArgs A)
         const float rho_a = 0.5f * (A.f.rho[idx] + A.f.rho[idx + o]);
         const float kap_a = 0.5f * (A.f.kap[idx] + A.f.kap[idx + o]);
         const float Q = rho_a * (1.0f + kap_a * pbar);
-        const float lva = lv[a * st + idx];
+        float lva = lv[a * st + idx];
+        if (DEFER_A3) {
+            lva -= dplus(A.lDp + a * st, g, A.f.g, A.f.g11, a, nd, idx);
+            lv[a * st + idx] = lva;
+        }
         const float lS = -A.f.dt * lva / Q;
         const float lQ = A.f.dt * Sv * lva / (Q * Q);
         float lD = w * lS;
@@ -198,7 +205,9 @@ __global__ void adj_receivers(float *lp, const SparseArgs r, const float *__rest
 }
 
 // A2: gather of the velocity-phase adjoints, then the pressure phase reversed.
-template <int ND, int L>
+// WITH_A0: then A0 of the step before at the same point, from the state sq
+// (S of this step is read before that of the step before overwrites it).
+template <int ND, int L, bool WITH_A0>
 __global__ void __launch_bounds__(kABX *kABY) adj_pressure(const AdjArgs A)
 {
     constexpr int nd = ND;
@@ -237,20 +246,23 @@ __global__ void __launch_bounds__(kABX *kABY) adj_pressure(const AdjArgs A)
         }
         A.lDp[a * st + idx] = lD;
     }
-}
-
-// A3: lam_v_a -= D^+(lam_D_a) at v points inside the grid.
-template <int ND, int L>
-__global__ void __launch_bounds__(kABX *kABY) adj_vel_from_p(const AdjArgs A)
-{
-    constexpr int nd = ND;
-    ADJ_POINT
-    const int64_t st = g.stride;
-    float *lv = A.lp + st;
+    if (WITH_A0) {
+        const float *vq = A.sq + st;
+        const float *m2q = A.sq + (int64_t)(1 + nd + nd * L) * st;
+        float S0 = 0.0f;
 #pragma unroll
-    for (int a = 0; a < nd; ++a) {
-        if (c3[a] == g.n[a] - 1) continue;
-        lv[a * st + idx] -= dplus(A.lDp + a * st, g, A.f.g, A.f.g11, a, nd, idx);
+        for (int a = 0; a < nd; ++a) {
+            const float D = dminus(vq + a * st, g, A.f.g, A.f.g11, a, nd, idx);
+            const int t = slot_p(c3[a], g.n[a], A.f.nb[a]) * A.f.n_labels + lab;
+            float Sa = A.f.w2[a][t] * D;
+#pragma unroll
+            for (int nu = 0; nu < L; ++nu) Sa += m2q[(int64_t)(a * L + nu) * st + idx];
+            S0 += Sa;
+        }
+        const float q0 = A.sq[idx];
+        const float K0 = x * (1.0f + q * q0);
+        A.pp[idx] = q0 - A.f.dt * S0 / K0;
+        A.sS[idx] = S0;
     }
 }
 
@@ -756,15 +768,18 @@ hipError_t adjoint_step_2d(AdjSweep A, const SparseArgs &src, const float *state
 
 namespace {
 
-// one thread per point, the four phases in turn
+// One thread per point.  A3 of each step is deferred into the velocity
+// kernel of the next call; A0 of the step before is fused into the pressure
+// kernel when its state is given, else run at the start of the next call.
 template <int ND, int L>
 hipError_t adjoint_step_points(const StepArgs &f, const SparseArgs &src, const SparseArgs &rcv, const float *state,
-                               const AdjointBuffers &b, long long step, const float *residual, hipStream_t st,
-                               bool *pp_next)
+                               const float *state_prev, const AdjointBuffers &b, long long step, bool have_pp,
+                               const float *residual, hipStream_t st, bool *pp_next)
 {
     AdjArgs A;
     A.f = f;
     A.sp = state;
+    A.sq = state_prev;
     A.lp = b.lp;
     A.pp = b.pp;
     A.sS = b.sS;
@@ -775,15 +790,23 @@ hipError_t adjoint_step_points(const StepArgs &f, const SparseArgs &src, const S
     A.gk = b.gk;
     const Geometry &g = f.geo;
     dim3 block(kABX, kABY), grid((g.n[0] + kABX - 1) / kABX, (g.n[1] + kABY - 1) / kABY, g.n[2]);
-    hipLaunchKernelGGL((adj_forward_p<ND, L>), grid, block, 0, st, A);
-    if (src.n > 0 && step < src.n_t)
-        hipLaunchKernelGGL(adj_sources, dim3((src.n + 255) / 256), dim3(256), 0, st, b.pp, src, step);
-    hipLaunchKernelGGL((adj_velocity<ND, L>), grid, block, 0, st, A);
+    if (!have_pp) {
+        hipLaunchKernelGGL((adj_forward_p<ND, L>), grid, block, 0, st, A);
+        if (src.n > 0 && step < src.n_t)
+            hipLaunchKernelGGL(adj_sources, dim3((src.n + 255) / 256), dim3(256), 0, st, b.pp, src, step);
+    }
+    hipLaunchKernelGGL((adj_velocity<ND, L, true>), grid, block, 0, st, A);
     if (rcv.n > 0 && residual)
         hipLaunchKernelGGL(adj_receivers, dim3((rcv.n + 255) / 256), dim3(256), 0, st, b.lp, rcv, residual);
-    hipLaunchKernelGGL((adj_pressure<ND, L>), grid, block, 0, st, A);
-    hipLaunchKernelGGL((adj_vel_from_p<ND, L>), grid, block, 0, st, A);
-    *pp_next = false;
+    if (state_prev && step >= 1) {
+        hipLaunchKernelGGL((adj_pressure<ND, L, true>), grid, block, 0, st, A);
+        if (src.n > 0 && step - 1 < src.n_t)
+            hipLaunchKernelGGL(adj_sources, dim3((src.n + 255) / 256), dim3(256), 0, st, b.pp, src, step - 1);
+        *pp_next = true;
+    } else {
+        hipLaunchKernelGGL((adj_pressure<ND, L, false>), grid, block, 0, st, A);
+        *pp_next = false;
+    }
     return hipGetLastError();
 }
 
@@ -815,19 +838,16 @@ hipError_t launch_adjoint_step(const StepArgs &f, const SparseArgs &src, const S
         default: return hipErrorInvalidValue;
         }
     }
-#else
-    (void)state_prev;
-    (void)have_pp;
 #endif
     switch (f.geo.ndim * 8 + L) {
-    case 2 * 8 + 1: return adjoint_step_points<2, 1>(f, src, rcv, state, b, step, residual, st, pp_next);
-    case 2 * 8 + 2: return adjoint_step_points<2, 2>(f, src, rcv, state, b, step, residual, st, pp_next);
-    case 2 * 8 + 3: return adjoint_step_points<2, 3>(f, src, rcv, state, b, step, residual, st, pp_next);
-    case 2 * 8 + 4: return adjoint_step_points<2, 4>(f, src, rcv, state, b, step, residual, st, pp_next);
-    case 3 * 8 + 1: return adjoint_step_points<3, 1>(f, src, rcv, state, b, step, residual, st, pp_next);
-    case 3 * 8 + 2: return adjoint_step_points<3, 2>(f, src, rcv, state, b, step, residual, st, pp_next);
-    case 3 * 8 + 3: return adjoint_step_points<3, 3>(f, src, rcv, state, b, step, residual, st, pp_next);
-    case 3 * 8 + 4: return adjoint_step_points<3, 4>(f, src, rcv, state, b, step, residual, st, pp_next);
+    case 2 * 8 + 1: return adjoint_step_points<2, 1>(f, src, rcv, state, state_prev, b, step, have_pp, residual, st, pp_next);
+    case 2 * 8 + 2: return adjoint_step_points<2, 2>(f, src, rcv, state, state_prev, b, step, have_pp, residual, st, pp_next);
+    case 2 * 8 + 3: return adjoint_step_points<2, 3>(f, src, rcv, state, state_prev, b, step, have_pp, residual, st, pp_next);
+    case 2 * 8 + 4: return adjoint_step_points<2, 4>(f, src, rcv, state, state_prev, b, step, have_pp, residual, st, pp_next);
+    case 3 * 8 + 1: return adjoint_step_points<3, 1>(f, src, rcv, state, state_prev, b, step, have_pp, residual, st, pp_next);
+    case 3 * 8 + 2: return adjoint_step_points<3, 2>(f, src, rcv, state, state_prev, b, step, have_pp, residual, st, pp_next);
+    case 3 * 8 + 3: return adjoint_step_points<3, 3>(f, src, rcv, state, state_prev, b, step, have_pp, residual, st, pp_next);
+    case 3 * 8 + 4: return adjoint_step_points<3, 4>(f, src, rcv, state, state_prev, b, step, have_pp, residual, st, pp_next);
     default: return hipErrorInvalidValue;
     }
 }
