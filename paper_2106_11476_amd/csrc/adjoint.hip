@@ -27,13 +27,33 @@
 // compile-time switch.
 #include "kernels.hpp"
 
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 
 namespace fw2 {
 
 namespace {
 
-constexpr int kABX = 64, kABY = 4;
+constexpr int kABX = 256, kABY = 1;       // default block of the per-point kernels (measured best)
+
+// Block shape of the per-point kernels: FW2_ADJ_BLOCK="bx,by" with bx * by =
+// 256 (a tuning knob), else kABX x kABY.
+dim3 adj_block()
+{
+    static dim3 b = [] {
+        int bx = kABX, by = kABY;
+        if (const char *e = std::getenv("FW2_ADJ_BLOCK")) {
+            int x = 0, y = 0;
+            if (std::sscanf(e, "%d,%d", &x, &y) == 2 && x > 0 && y > 0 && x * y == kABX * kABY) {
+                bx = x;
+                by = y;
+            }
+        }
+        return dim3(bx, by);
+    }();
+    return b;
+}
 
 struct AdjArgs {
     StepArgs f;              // medium, tables, stencil of the domain (f.p etc. unused)
@@ -93,8 +113,8 @@ __device__ __forceinline__ int slot_v(int x, int n, int nb) { return max(max(nb 
 
 #define ADJ_POINT                                                                  \
     const Geometry &g = A.f.geo;                                                   \
-    const int i = blockIdx.x * kABX + threadIdx.x;                                 \
-    const int j = blockIdx.y * kABY + threadIdx.y;                                 \
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;                           \
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;                           \
     const int k = blockIdx.z;                                                      \
     if (i >= g.n[0] || j >= g.n[1]) return;                                        \
     const int c3[3] = {i, j, k};                                                   \
@@ -789,7 +809,8 @@ hipError_t adjoint_step_points(const StepArgs &f, const SparseArgs &src, const S
     A.lDp = b.lDp;
     A.gk = b.gk;
     const Geometry &g = f.geo;
-    dim3 block(kABX, kABY), grid((g.n[0] + kABX - 1) / kABX, (g.n[1] + kABY - 1) / kABY, g.n[2]);
+    const dim3 block = adj_block();
+    const dim3 grid((g.n[0] + block.x - 1) / block.x, (g.n[1] + block.y - 1) / block.y, g.n[2]);
     if (!have_pp) {
         hipLaunchKernelGGL((adj_forward_p<ND, L>), grid, block, 0, st, A);
         if (src.n > 0 && step < src.n_t)
@@ -860,7 +881,8 @@ hipError_t launch_adjoint_gradient(const StepArgs &f, const AdjointBuffers &b, h
     A.f = f;
     A.gk = b.gk;
     const Geometry &g = f.geo;
-    dim3 block(kABX, kABY), grid((g.n[0] + kABX - 1) / kABX, (g.n[1] + kABY - 1) / kABY, g.n[2]);
+    const dim3 block = adj_block();
+    const dim3 grid((g.n[0] + block.x - 1) / block.x, (g.n[1] + block.y - 1) / block.y, g.n[2]);
     hipLaunchKernelGGL(adj_grad_c, grid, block, 0, st, A, b.out);
     return hipGetLastError();
 }
