@@ -484,12 +484,12 @@ fw2_status fw2_create_domain(const fw2_domain_desc *desc, void *dev_workspace, u
         a.w1[ax] = a.w2[ax] = nullptr;
     }
 
-    d->kc = nd == 2 ? fw2::KernelConfig{1, 256, 4} : fw2::KernelConfig{1, 32, 16};
+    d->kc = nd == 2 ? fw2::KernelConfig{1, 256, 4} : fw2::KernelConfig{2, 64, 64};
     if (const char *ev = std::getenv("FW2_KERNEL_CONFIG")) {      // "variant,bx,rows" (tuning runs)
         int v = 0, bx = 0, ry = 0;
         const bool parsed = std::sscanf(ev, "%d,%d,%d", &v, &bx, &ry) == 3;
         const bool ok2 = nd == 2 && (v == 0 || v == 1 || v == 2) && (bx == 64 || bx == 128 || bx == 256);
-        const bool ok3 = nd == 3 && (v == 0 || (v == 1 && (bx == 16 || bx == 32 || bx == 64)));
+        const bool ok3 = nd == 3 && (v == 0 || ((v == 1 || v == 2) && (bx == 16 || bx == 32 || bx == 64)));
         if (parsed && (ok2 || ok3) && ry >= 1 && ry <= 1024)
             d->kc = fw2::KernelConfig{v, bx, ry};
     }

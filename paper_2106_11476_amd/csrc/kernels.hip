@@ -544,7 +544,40 @@ __device__ __forceinline__ void stage(float *dst, const float *__restrict__ f, c
     }
 }
 
-template <int L, bool CENTRED, int BX, int BY, bool PP>
+// The same staging in two halves, for prefetching: the elements a thread
+// stages (e = tid + q NT) are loaded into registers one plane ahead and
+// stored into LDS in the next iteration.
+template <int W, int H, int NT>
+struct Staged {
+    static constexpr int N = (W * H + NT - 1) / NT;
+    float r[N];
+};
+
+template <int W, int H, int NT>
+__device__ __forceinline__ void stage_load(Staged<W, H, NT> &s, const float *__restrict__ f, const Geometry &g,
+                                           int xs, int ys, int z, int tid)
+{
+#pragma unroll
+    for (int q = 0; q < Staged<W, H, NT>::N; ++q) {
+        const int e = tid + q * NT;
+        if (e < W * H) {
+            const int r = e / W, c = e - r * W;
+            s.r[q] = ldz3(f, g, xs + c, ys + r, z);
+        }
+    }
+}
+
+template <int W, int H, int NT>
+__device__ __forceinline__ void stage_store(float *dst, const Staged<W, H, NT> &s, int tid)
+{
+#pragma unroll
+    for (int q = 0; q < Staged<W, H, NT>::N; ++q) {
+        const int e = tid + q * NT;
+        if (e < W * H) dst[e] = s.r[q];
+    }
+}
+
+template <int L, bool CENTRED, int BX, int BY, bool PP, bool PF>
 __global__ void __launch_bounds__(BX *BY) pressure_sweep3d(const StepArgs a, int rows, int nbx, int nby, int nblocks)
 {
     constexpr int NT = BX * BY;
@@ -582,29 +615,71 @@ __global__ void __launch_bounds__(BX *BY) pressure_sweep3d(const StepArgs a, int
     const int s0 = max(max(a.nb[0] - i, i - (nx - 1 - a.nb[0])), 0);
     const int s1 = max(max(a.nb[1] - j, j - (ny - 1 - a.nb[1])), 0);
     const int zend = min(z0 + rows, nz);
-    for (int k = z0; k < zend; ++k) {
-        stage<XW, XH, NT>(sx[(k + 1) & 3], vx, g, x0 - 4, y0 - 1, k + 1, tid);
-        stage<YW, YH, NT>(sy[(k + 1) & 3], vy, g, x0 - 1, y0 - 4, k + 1, tid);
-        stage<ZW, ZH, NT>(sz[k % 3], vz, g, x0 - 1, y0 - 1, k, tid);
-        const float vzn = ldz3(vz, g, i, j, k + 3);
-        const int64_t idx = g.origin + (int64_t)k * g.plane + (int64_t)j * g.pitch + i;
-        float p0 = 0.0f, k0 = 1.0f, q0 = 0.0f, r0 = 1.0f;
+    // what one plane k needs from global memory besides the staged planes
+    struct Own {
+        float vzn, p0, k0, q0, r0;
+        int l;
         float m[3][L];
-        int l = 0;
-        if (live) {
-            p0 = a.p[idx];
-            k0 = a.kap[idx];
-            q0 = a.nlq[idx];
-            if (PP) r0 = a.rho[idx];
-            l = a.label ? (int)a.label[idx] : 0;
+    };
+    auto load_own = [&](Own &o, int k) {
+        o.vzn = ldz3(vz, g, i, j, k + 3);
+        o.p0 = 0.0f;
+        o.k0 = 1.0f;
+        o.q0 = 0.0f;
+        o.r0 = 1.0f;
+        o.l = 0;
+        if (live && k < nz) {
+            const int64_t idx = g.origin + (int64_t)k * g.plane + (int64_t)j * g.pitch + i;
+            o.p0 = a.p[idx];
+            o.k0 = a.kap[idx];
+            o.q0 = a.nlq[idx];
+            if (PP) o.r0 = a.rho[idx];
+            o.l = a.label ? (int)a.label[idx] : 0;
 #pragma unroll
             for (int ax = 0; ax < 3; ++ax)
 #pragma unroll
-                for (int nu = 0; nu < L; ++nu) m[ax][nu] = a.psi2[(int64_t)(ax * L + nu) * g.stride + idx];
+                for (int nu = 0; nu < L; ++nu) o.m[ax][nu] = a.psi2[(int64_t)(ax * L + nu) * g.stride + idx];
         }
+    };
+    Staged<XW, XH, NT> px;
+    Staged<YW, YH, NT> py;
+    Staged<ZW, ZH, NT> pz;
+    Own cur;
+    if (PF) {                                   // plane z0: staged x/y planes z0 + 1, z plane z0
+        stage_load<XW, XH, NT>(px, vx, g, x0 - 4, y0 - 1, z0 + 1, tid);
+        stage_load<YW, YH, NT>(py, vy, g, x0 - 1, y0 - 4, z0 + 1, tid);
+        stage_load<ZW, ZH, NT>(pz, vz, g, x0 - 1, y0 - 1, z0, tid);
+        load_own(cur, z0);
+    }
+    for (int k = z0; k < zend; ++k) {
+        if (PF) {
+            stage_store<XW, XH, NT>(sx[(k + 1) & 3], px, tid);
+            stage_store<YW, YH, NT>(sy[(k + 1) & 3], py, tid);
+            stage_store<ZW, ZH, NT>(sz[k % 3], pz, tid);
+        } else {
+            stage<XW, XH, NT>(sx[(k + 1) & 3], vx, g, x0 - 4, y0 - 1, k + 1, tid);
+            stage<YW, YH, NT>(sy[(k + 1) & 3], vy, g, x0 - 1, y0 - 4, k + 1, tid);
+            stage<ZW, ZH, NT>(sz[k % 3], vz, g, x0 - 1, y0 - 1, k, tid);
+            load_own(cur, k);
+        }
+        const Own o = cur;
+        if (PF && k + 1 < zend) {               // next plane's loads in flight during this one
+            stage_load<XW, XH, NT>(px, vx, g, x0 - 4, y0 - 1, k + 2, tid);
+            stage_load<YW, YH, NT>(py, vy, g, x0 - 1, y0 - 4, k + 2, tid);
+            stage_load<ZW, ZH, NT>(pz, vz, g, x0 - 1, y0 - 1, k + 1, tid);
+            load_own(cur, k + 1);
+        }
+        const int64_t idx = g.origin + (int64_t)k * g.plane + (int64_t)j * g.pitch + i;
+        const float p0 = o.p0, k0 = o.k0, q0 = o.q0, r0 = o.r0;
+        const int l = o.l;
+        float m[3][L];
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax)
+#pragma unroll
+            for (int nu = 0; nu < L; ++nu) m[ax][nu] = o.m[ax][nu];
 #pragma unroll
         for (int q = 0; q < 7; ++q) w[q] = w[q + 1];
-        w[7] = vzn;
+        w[7] = o.vzn;
         __syncthreads();
         if (live) {
             const Wts W = weights<PP>(a, PP ? cell_r2(a, r0, k0) : 0.0f);
@@ -659,7 +734,7 @@ __global__ void __launch_bounds__(BX *BY) pressure_sweep3d(const StepArgs a, int
     }
 }
 
-template <int L, bool CENTRED, int BX, int BY, bool PP>
+template <int L, bool CENTRED, int BX, int BY, bool PP, bool PF>
 __global__ void __launch_bounds__(BX *BY) velocity_sweep3d(const StepArgs a, int rows, int nbx, int nby, int nblocks)
 {
     constexpr int NT = BX * BY;
@@ -692,27 +767,64 @@ __global__ void __launch_bounds__(BX *BY) velocity_sweep3d(const StepArgs a, int
     const int s0 = max(max(a.nb[0] - i, i - (nx - 2 - a.nb[0])), 0);
     const int s1 = max(max(a.nb[1] - j, j - (ny - 2 - a.nb[1])), 0);
     const int zend = min(z0 + rows, nz);
-    for (int k = z0; k < zend; ++k) {
-        stage<PW, PH, NT>(sp[(k + 1) & 3], pp, g, x0 - 4, y0 - 4, k + 1, tid);
-        stage<RW, RH, NT>(sr[(k + 1) % 3], a.rho, g, x0, y0, k + 1, tid);
-        stage<RW, RH, NT>(sk[(k + 1) % 3], a.kap, g, x0, y0, k + 1, tid);
-        const float pn = ldz3(pp, g, i, j, k + 4);
-        const int64_t idx = g.origin + (int64_t)k * g.plane + (int64_t)j * g.pitch + i;
-        float u[3] = {0.0f, 0.0f, 0.0f};
+    struct Own {
+        float pn, u[3];
+        int l;
         float m[3][L];
-        int l = 0;
-        if (live) {
+    };
+    auto load_own = [&](Own &o, int k) {
+        o.pn = ldz3(pp, g, i, j, k + 4);
+        o.u[0] = o.u[1] = o.u[2] = 0.0f;
+        o.l = 0;
+        if (live && k < nz) {
+            const int64_t idx = g.origin + (int64_t)k * g.plane + (int64_t)j * g.pitch + i;
 #pragma unroll
-            for (int ax = 0; ax < 3; ++ax) u[ax] = a.v[(int64_t)ax * g.stride + idx];
-            l = a.label ? (int)a.label[idx] : 0;
+            for (int ax = 0; ax < 3; ++ax) o.u[ax] = a.v[(int64_t)ax * g.stride + idx];
+            o.l = a.label ? (int)a.label[idx] : 0;
 #pragma unroll
             for (int ax = 0; ax < 3; ++ax)
 #pragma unroll
-                for (int nu = 0; nu < L; ++nu) m[ax][nu] = a.psi1[(int64_t)(ax * L + nu) * g.stride + idx];
+                for (int nu = 0; nu < L; ++nu) o.m[ax][nu] = a.psi1[(int64_t)(ax * L + nu) * g.stride + idx];
         }
+    };
+    Staged<PW, PH, NT> ps;
+    Staged<RW, RH, NT> rs, ks;
+    Own cur;
+    if (PF) {
+        stage_load<PW, PH, NT>(ps, pp, g, x0 - 4, y0 - 4, z0 + 1, tid);
+        stage_load<RW, RH, NT>(rs, a.rho, g, x0, y0, z0 + 1, tid);
+        stage_load<RW, RH, NT>(ks, a.kap, g, x0, y0, z0 + 1, tid);
+        load_own(cur, z0);
+    }
+    for (int k = z0; k < zend; ++k) {
+        if (PF) {
+            stage_store<PW, PH, NT>(sp[(k + 1) & 3], ps, tid);
+            stage_store<RW, RH, NT>(sr[(k + 1) % 3], rs, tid);
+            stage_store<RW, RH, NT>(sk[(k + 1) % 3], ks, tid);
+        } else {
+            stage<PW, PH, NT>(sp[(k + 1) & 3], pp, g, x0 - 4, y0 - 4, k + 1, tid);
+            stage<RW, RH, NT>(sr[(k + 1) % 3], a.rho, g, x0, y0, k + 1, tid);
+            stage<RW, RH, NT>(sk[(k + 1) % 3], a.kap, g, x0, y0, k + 1, tid);
+            load_own(cur, k);
+        }
+        const Own o = cur;
+        if (PF && k + 1 < zend) {
+            stage_load<PW, PH, NT>(ps, pp, g, x0 - 4, y0 - 4, k + 2, tid);
+            stage_load<RW, RH, NT>(rs, a.rho, g, x0, y0, k + 2, tid);
+            stage_load<RW, RH, NT>(ks, a.kap, g, x0, y0, k + 2, tid);
+            load_own(cur, k + 1);
+        }
+        const int64_t idx = g.origin + (int64_t)k * g.plane + (int64_t)j * g.pitch + i;
+        const float u[3] = {o.u[0], o.u[1], o.u[2]};
+        const int l = o.l;
+        float m[3][L];
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax)
+#pragma unroll
+            for (int nu = 0; nu < L; ++nu) m[ax][nu] = o.m[ax][nu];
 #pragma unroll
         for (int q = 0; q < 7; ++q) w[q] = w[q + 1];
-        w[7] = pn;
+        w[7] = o.pn;
         __syncthreads();
         if (live) {
             const float *P0 = sp[k & 3], *Pp = sp[(k + 1) & 3], *Pm = sp[(k + 3) & 3];
@@ -850,7 +962,7 @@ hipError_t launch_sweep(const StepArgs &a, bool pressure, const KernelConfig &kc
     return hipErrorInvalidValue;
 }
 
-template <int L, bool C, bool PP>
+template <int L, bool C, bool PP, bool PF>
 hipError_t launch_sweep3(const StepArgs &a, bool pressure, const KernelConfig &kc, hipStream_t st)
 {
 #define FW2_SWEEP3(BXV, BYV)                                                                            \
@@ -859,10 +971,10 @@ hipError_t launch_sweep3(const StepArgs &a, bool pressure, const KernelConfig &k
         const int nbz = (a.geo.n[2] + kc.rows - 1) / kc.rows;                                           \
         const int nblocks = nbx * nby * nbz;                                                            \
         if (pressure)                                                                                   \
-            hipLaunchKernelGGL((pressure_sweep3d<L, C, BXV, BYV, PP>), dim3(nblocks), dim3(BXV * BYV), 0, st, \
+            hipLaunchKernelGGL((pressure_sweep3d<L, C, BXV, BYV, PP, PF>), dim3(nblocks), dim3(BXV * BYV), 0, st, \
                                a, kc.rows, nbx, nby, nblocks);                                          \
         else                                                                                            \
-            hipLaunchKernelGGL((velocity_sweep3d<L, C, BXV, BYV, PP>), dim3(nblocks), dim3(BXV * BYV), 0, st, \
+            hipLaunchKernelGGL((velocity_sweep3d<L, C, BXV, BYV, PP, PF>), dim3(nblocks), dim3(BXV * BYV), 0, st, \
                                a, kc.rows, nbx, nby, nblocks);                                          \
         return hipGetLastError();                                                                       \
     }
@@ -996,7 +1108,8 @@ hipError_t launch_v(const StepArgs &a, hipStream_t st)
 template <bool P, int NDIM, int L, bool C, bool PP>
 hipError_t dispatch_variant(const StepArgs &a, const KernelConfig &kc, hipStream_t st)
 {
-    if (NDIM == 3 && kc.variant == 1) return launch_sweep3<L, C, PP>(a, P, kc, st);
+    if (NDIM == 3 && kc.variant == 1) return launch_sweep3<L, C, PP, false>(a, P, kc, st);
+    if (NDIM == 3 && kc.variant == 2) return launch_sweep3<L, C, PP, true>(a, P, kc, st);
     if (NDIM == 2 && kc.variant == 1) return launch_sweep<L, C, false, PP>(a, P, kc, st);
     if (NDIM == 2 && kc.variant == 2) return launch_sweep<L, C, true, PP>(a, P, kc, st);
     return P ? launch_p<NDIM, L, C, PP>(a, st) : launch_v<NDIM, L, C, PP>(a, st);

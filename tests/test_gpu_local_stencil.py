@@ -30,7 +30,7 @@ def test_local_stencil_2d_matches_oracle(monkeypatch, config, shape, L, scheme):
     compare(f, tr, ref, rtr, "local %s %s" % (config, shape), prob=prob)
 
 
-@pytest.mark.parametrize("config", ["0,32,16", "1,32,16", "1,64,5", "1,16,7"])
+@pytest.mark.parametrize("config", ["0,32,16", "1,32,16", "1,64,5", "1,16,7", "2,32,16"])
 @pytest.mark.parametrize("shape,L,scheme", [((37, 21, 19), 2, 1), ((33, 20, 21), 4, 0)])
 def test_local_stencil_3d_matches_oracle(monkeypatch, config, shape, L, scheme):
     monkeypatch.setenv("FW2_KERNEL_CONFIG", config)

@@ -296,11 +296,12 @@ def test_kernel_timing_counts_launches():
 
 # ------------------------------------------------- kernel variants / tiles ---
 
-@pytest.mark.parametrize("config", ["0,32,16", "1,32,16", "1,64,5", "1,32,1", "1,16,7"])
+@pytest.mark.parametrize("config", ["0,32,16", "1,32,16", "1,64,5", "1,32,1", "1,16,7", "2,32,16", "2,64,5", "2,16,1"])
 @pytest.mark.parametrize("shape,L,scheme", [((37, 21, 19), 2, 1), ((70, 33, 24), 3, 0), ((16, 16, 40), 1, 1)])
 def test_3d_kernel_variants_match_oracle(monkeypatch, config, shape, L, scheme):
     """3D plane-sweep tiles (32x16 and 64x8 columns, ragged in every axis,
-    one-plane tiles) and the generic kernel give oracle results."""
+    one-plane tiles), with and without the plane prefetch (variant 2), and
+    the generic kernel give oracle results."""
     monkeypatch.setenv("FW2_KERNEL_CONFIG", config)
     prob = W.random_medium(shape, L, 3, seed=9, nb=5, ntr=3)
     prob.relax_scheme = scheme
