@@ -296,7 +296,7 @@ def summarize_stats_only(stats_db, name, title, commands):
         fh.write("\n".join(lines) + "\n")
 
 
-def summarize_profiles(stats_db, fetch_db, write_db, workload, copy_bytes, commands):
+def summarize_profiles(stats_db, fetch_db, write_db, workload, copy_bytes, commands, n3d=1024):
     """Write profiles/*.txt from rocprofv3 results (kernel-trace stats and the
     FETCH_SIZE / WRITE_SIZE passes).  Counter values are KiB per dispatch;
     each is scaled by what it reads for the plain copy that reads and writes
@@ -319,10 +319,10 @@ def summarize_profiles(stats_db, fetch_db, write_db, workload, copy_bytes, comma
     lines.append("%-70s %8s %12s %10s" % ("kernel", "calls", "total_us", "avg_us"))
     for name, calls, tot, avg in stats:
         lines.append("%-70s %8d %12.1f %10.3f" % (name[:70], calls, tot, avg))
-    with open(os.path.join(PROFILES, "kernel_stats_%s.txt" % workload), "w") as fh:
+    name = workload if workload != "skull_3d" else "skull_3d_%d" % n3d
+    with open(os.path.join(PROFILES, "kernel_stats_%s.txt" % name), "w") as fh:
         fh.write("\n".join(lines) + "\n")
-    import workloads as W
-    prob = make_workload(workload) if workload in ("abdominal_2d", "plain_2d") else None
+    prob = make_workload(workload, n3d)
     labels = prob.label is not None and np.asarray(prob.relax_table).shape[0] > 1
     p_b, v_b, _ = kernel_bytes(prob.ndim, prob.n_relax, labels)
     # the benchmark's sweep kernels carry the mechanism count as their first
@@ -385,7 +385,7 @@ def main():
         summarize_stats_only(*args.summarize_stats, commands=args.commands)
         return
     if args.summarize:
-        summarize_profiles(*args.summarize, workload=args.workload, copy_bytes=args.copy_read_bytes,
+        summarize_profiles(*args.summarize, workload=args.workload, n3d=args.n3d, copy_bytes=args.copy_read_bytes,
                            commands=args.commands)
         return
     if args.gpus != 1:
