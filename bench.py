@@ -159,6 +159,7 @@ def serving_leg(seed=4):
             "capacity_gpoint_updates_per_s": {"plain": round(upd / p0.makespan / 1e9, 3),
                                               "batched": round(upd / b0.makespan / 1e9, 3)},
             "capacity_speedup": round(p0.makespan / b0.makespan, 3),
+            "capacity_host_s": {"plain": p0.summary()["host_s"], "batched": b0.summary()["host_s"]},
             "poisson_rate_per_s": round(lam, 3),
             "poisson": {"plain": pl.summary(), "batched": bt.summary()},
         }

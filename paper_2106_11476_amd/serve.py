@@ -65,6 +65,13 @@ class Stats:
     latencies: List[float] = field(default_factory=list)
     peak_bytes: int = 0
     peak_active: int = 0
+    # host time by activity (s): building domains, batch table updates,
+    # waiting for the device, handing back finished requests
+    t_build: float = 0.0
+    t_table: float = 0.0
+    t_wait: float = 0.0
+    t_finish: float = 0.0
+    chunks: int = 0
 
     def summary(self):
         lat = np.asarray(self.latencies) if self.latencies else np.zeros(1)
@@ -72,7 +79,10 @@ class Stats:
                 "sims_per_s": round(self.completed / self.makespan, 4) if self.makespan > 0 else None,
                 "p50_latency_s": round(float(np.percentile(lat, 50)), 4),
                 "p99_latency_s": round(float(np.percentile(lat, 99)), 4),
-                "peak_resident_bytes": int(self.peak_bytes), "peak_active": int(self.peak_active)}
+                "peak_resident_bytes": int(self.peak_bytes), "peak_active": int(self.peak_active),
+                "host_s": {"build": round(self.t_build, 4), "table": round(self.t_table, 4),
+                           "wait": round(self.t_wait, 4), "finish": round(self.t_finish, 4)},
+                "chunks": int(self.chunks)}
 
 
 class Server:
@@ -82,11 +92,13 @@ class Server:
     max_active   -- largest number of requests advanced by one launch (<= 64)
     chunk        -- steps between admission / completion points
 
-    Host work overlaps device work: while a chunk of steps runs on the batch
-    stream, arrived requests are admitted (arrival order, memory budget and
-    slots counted over running and staged requests) and their domains are
-    built on a separate setup stream; they join the batch at the next chunk
-    boundary, when finished requests also hand back their traces.
+    Host work overlaps device work: arrived requests are admitted (arrival
+    order, memory budget and slots counted over running, built and admitted
+    requests); their domains are built on a separate setup stream while a
+    chunk of steps runs on the batch stream, and join the batch at the next
+    chunk boundary, when finished requests also hand back their traces.  With
+    requests waiting to be built, chunks are kept short so that they join
+    early.
     """
 
     def __init__(self, budget_bytes, max_active=32, chunk=64, device="cuda:0", tile=(256, 4)):
@@ -117,26 +129,43 @@ class Server:
                 raise ValueError("request %d needs %d bytes, above the budget" % (r.rid, r.footprint))
         active = []               # (request, domain) in the batch
         staged = []               # (request, domain) built, joining at the next boundary
+        pending = []              # admitted requests (memory reserved) not built yet
         in_flight = False         # a chunk is queued on the batch stream
         stats = Stats()
         t0 = clock()
-        while queue or active or staged:
-            # admit and build while the chunk in flight runs
-            now = clock() - t0
-            held = active + staged
-            new = admit(queue, sum(r.footprint for r, _ in held), self.budget,
-                        self.max_active - len(held), now)
+
+        def build_one():
+            r = pending.pop(0)
+            tb = clock()
+            staged.append((r, self._start(r)))
+            stats.t_build += clock() - tb
+
+        while queue or active or staged or pending:
+            # admit arrived requests (arrival order; memory and slots counted
+            # over running, built and admitted-but-unbuilt requests)
+            held = [r for r, _ in active] + [r for r, _ in staged] + pending
+            new = admit(queue, sum(r.footprint for r in held), self.budget, self.max_active - len(held),
+                        clock() - t0)
             for r in new:
                 queue.remove(r)
                 r.admitted = clock() - t0
-                staged.append((r, self._start(r)))
+                pending.append(r)
+            # build while the device is busy with the chunk in flight; with an
+            # idle device build one, so that stepping can start
+            if pending and not (in_flight or active or staged):
+                build_one()
+            while pending and in_flight and not self.stream.query():
+                build_one()
             changed = False
             finished = []
             if in_flight:
+                tw = clock()
                 self.stream.synchronize()
+                stats.t_wait += clock() - tw
                 in_flight = False
                 finished = [(r, d) for r, d in active if d.current_step() >= r.n_steps]
                 if finished:
+                    tf = clock()
                     active = [(r, d) for r, d in active if d.current_step() < r.n_steps]
                     changed = True
                     for r, d in finished:
@@ -144,28 +173,33 @@ class Server:
                         r.done = clock() - t0
                         stats.latencies.append(r.done - r.arrival)
                         stats.completed += 1
+                    stats.t_finish += clock() - tf
             if staged:
                 active += staged
                 staged = []
                 changed = True
             if changed:
+                tt = clock()
                 # the batch table stops referring to finished domains before they go
                 self.batch.set_domains([d for _, d in active], [r.n_steps for r, _ in active])
                 for _, d in finished:
                     d.destroy_domain()
+                stats.t_table += clock() - tt
             if not active:
-                if queue:
+                if queue and not pending:
                     wait = queue[0].arrival - (clock() - t0)
                     if wait > 0:
                         time.sleep(min(wait, 0.05))
                 continue
             stats.peak_bytes = max(stats.peak_bytes, sum(r.footprint for r, _ in active))
             stats.peak_active = max(stats.peak_active, len(active))
-            # run until the next event: the first completion, or (when a slot is
-            # free and a request is queued) the next chunk boundary
+            # run until the next event: the first completion, or (when requests
+            # wait to join) the next chunk boundary
             to_done = min(r.n_steps - d.current_step() for r, d in active)
-            k = to_done if (not queue or len(active) >= self.max_active) else min(to_done, self.chunk)
+            waiting = pending or (queue and len(active) < self.max_active)
+            k = min(to_done, self.chunk) if waiting else to_done
             self.batch.step(max(int(k), 1))
+            stats.chunks += 1
             in_flight = True
         stats.makespan = clock() - t0
         return stats
@@ -186,14 +220,20 @@ def run_plain(requests, device="cuda:0", clock=time.perf_counter):
         if wait > 0:
             time.sleep(wait)
         r.admitted = clock() - t0
+        tb = clock()
         dom = fw2.Domain(r.problem, device=dev, stream=stream)
         if len(r.problem.src_idx):
             dom.add_source(r.problem.src_idx, r.problem.src_sig, r.problem.src_w, r.problem.signals)
         dom.add_receivers(r.problem.rcv_idx, r.n_steps)
+        stats.t_build += clock() - tb
         dom.step(r.n_steps)
+        tw = clock()
         stream.synchronize()
+        stats.t_wait += clock() - tw
+        tf = clock()
         r.trace = dom.trace.cpu().numpy()
         dom.destroy_domain()
+        stats.t_finish += clock() - tf
         r.done = clock() - t0
         stats.latencies.append(r.done - r.arrival)
         stats.completed += 1
