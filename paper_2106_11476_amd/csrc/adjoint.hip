@@ -139,7 +139,7 @@ __global__ void __launch_bounds__(kABX *kABY) adj_forward_p(const AdjArgs A)
         const int t = slot_p(c3[a], g.n[a], A.f.nb[a]) * A.f.n_labels + lab;
         float Sa = A.f.w2[a][t] * D;
 #pragma unroll
-        for (int nu = 0; nu < L; ++nu) Sa += m2[(int64_t)(a * L + nu) * st + idx];
+        for (int nu = 0; nu < L; ++nu) Sa += ntld(&m2[(int64_t)(a * L + nu) * st + idx]);
         S += Sa;
     }
     const float p0 = A.sp[idx];
@@ -190,7 +190,7 @@ __global__ void __launch_bounds__(kABX *kABY) adj_velocity(const AdjArgs A)
         const float w = A.f.w1[a][t];
         float Sv = w * D;
 #pragma unroll
-        for (int nu = 0; nu < L; ++nu) Sv += m1[(int64_t)(a * L + nu) * st + idx];
+        for (int nu = 0; nu < L; ++nu) Sv += ntld(&m1[(int64_t)(a * L + nu) * st + idx]);
         const float pbar = 0.5f * (A.pp[idx] + A.pp[idx + o]);
         const float rho_a = 0.5f * (A.f.rho[idx] + A.f.rho[idx + o]);
         const float kap_a = 0.5f * (A.f.kap[idx] + A.f.kap[idx + o]);
@@ -207,9 +207,9 @@ __global__ void __launch_bounds__(kABX *kABY) adj_velocity(const AdjArgs A)
         for (int nu = 0; nu < L; ++nu) {
             const int64_t c = (int64_t)(a * L + nu) * st + idx;
             const float2 q = bc[nu];
-            const float lmn = lm1[c];
+            const float lmn = ntld(&lm1[c]);
             lD = fmaf(q.y, lmn, lD);
-            lm1[c] = fmaf(q.x, lmn, lS);
+            ntst(&lm1[c], fmaf(q.x, lmn, lS));
         }
         oDv[idx] = lD;
         opb[idx] = lQ * rho_a * kap_a;
@@ -260,9 +260,9 @@ __global__ void __launch_bounds__(kABX *kABY) adj_pressure(const AdjArgs A)
         for (int nu = 0; nu < L; ++nu) {
             const int64_t c = (int64_t)(a * L + nu) * st + idx;
             const float2 qq = bc[nu];
-            const float lmn = lm2[c];
+            const float lmn = ntld(&lm2[c]);
             lD = fmaf(qq.y, lmn, lD);
-            lm2[c] = fmaf(qq.x, lmn, lS);
+            ntst(&lm2[c], fmaf(qq.x, lmn, lS));
         }
         A.lDp[a * st + idx] = lD;
     }
@@ -276,7 +276,7 @@ __global__ void __launch_bounds__(kABX *kABY) adj_pressure(const AdjArgs A)
             const int t = slot_p(c3[a], g.n[a], A.f.nb[a]) * A.f.n_labels + lab;
             float Sa = A.f.w2[a][t] * D;
 #pragma unroll
-            for (int nu = 0; nu < L; ++nu) Sa += m2q[(int64_t)(a * L + nu) * st + idx];
+            for (int nu = 0; nu < L; ++nu) Sa += ntld(&m2q[(int64_t)(a * L + nu) * st + idx]);
             S0 += Sa;
         }
         const float q0 = A.sq[idx];

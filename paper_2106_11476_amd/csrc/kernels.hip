@@ -112,10 +112,10 @@ __global__ void __launch_bounds__(kBX * kBY) pressure_kernel(const StepArgs a)
 #pragma unroll
             for (int nu = 0; nu < L; ++nu) {
                 const float2 q = bc[nu];
-                const float m = ps[nu * g.stride];
+                const float m = ntld(&ps[nu * g.stride]);
                 const float mn = fmaf(q.x, m, q.y * D);
                 Sa += CENTRED ? m : mn;
-                ps[nu * g.stride] = mn;
+                ntst(&ps[nu * g.stride], mn);
             }
             S += Sa;
         }
@@ -172,10 +172,10 @@ __global__ void __launch_bounds__(kBX * kBY) velocity_kernel(const StepArgs a)
 #pragma unroll
             for (int nu = 0; nu < L; ++nu) {
                 const float2 q = bc[nu];
-                const float m = ps[nu * g.stride];
+                const float m = ntld(&ps[nu * g.stride]);
                 const float mn = fmaf(q.x, m, q.y * D);
                 S += CENTRED ? m : mn;
-                ps[nu * g.stride] = mn;
+                ntst(&ps[nu * g.stride], mn);
             }
             const float pbar = 0.5f * (p0 + p1);
             const float rho_a = 0.5f * (r0 + a.rho[idx + o]);
@@ -263,7 +263,7 @@ __device__ __forceinline__ void p_load_row(PRow<L> &r, const StepArgs &a, int i,
 #pragma unroll
         for (int ax = 0; ax < 2; ++ax)
 #pragma unroll
-            for (int nu = 0; nu < L; ++nu) r.m[ax][nu] = a.psi2[(int64_t)(ax * L + nu) * g.stride + idx];
+            for (int nu = 0; nu < L; ++nu) r.m[ax][nu] = ntld(&a.psi2[(int64_t)(ax * L + nu) * g.stride + idx]);
     }
 }
 
@@ -348,7 +348,7 @@ __device__ __forceinline__ void pressure_tile2d(const StepArgs &a, int rows, int
 #pragma unroll
             for (int ax = 0; ax < 2; ++ax)
 #pragma unroll
-                for (int nu = 0; nu < L; ++nu) psi[(int64_t)(ax * L + nu) * g.stride + idx] = cur.m[ax][nu];
+                for (int nu = 0; nu < L; ++nu) ntst(&psi[(int64_t)(ax * L + nu) * g.stride + idx], cur.m[ax][nu]);
         }
         if (PF) cur = nxt;
     }
@@ -380,7 +380,7 @@ __device__ __forceinline__ void v_load_row(VRow<L> &r, const StepArgs &a, int i,
 #pragma unroll
         for (int ax = 0; ax < 2; ++ax)
 #pragma unroll
-            for (int nu = 0; nu < L; ++nu) r.m[ax][nu] = a.psi1[(int64_t)(ax * L + nu) * g.stride + idx];
+            for (int nu = 0; nu < L; ++nu) r.m[ax][nu] = ntld(&a.psi1[(int64_t)(ax * L + nu) * g.stride + idx]);
     }
 }
 
@@ -463,7 +463,7 @@ __device__ __forceinline__ void velocity_tile2d(const StepArgs &a, int rows, int
                 const float kap_a = 0.5f * (kk0[t] + kk0[t + 1]);
                 vx[idx] = cur.ux - a.dt * S / (rho_a * (1.0f + kap_a * pbar));
 #pragma unroll
-                for (int nu = 0; nu < L; ++nu) psi[(int64_t)nu * g.stride + idx] = cur.m[0][nu];
+                for (int nu = 0; nu < L; ++nu) ntst(&psi[(int64_t)nu * g.stride + idx], cur.m[0][nu]);
             }
             // v_y at (i, j + 1/2)
             if (j < ny - 1) {
@@ -490,7 +490,7 @@ __device__ __forceinline__ void velocity_tile2d(const StepArgs &a, int rows, int
                 const float kap_a = 0.5f * (kk0[t] + sk[(j + 1) % 3][t]);
                 vy[idx] = cur.uy - a.dt * S / (rho_a * (1.0f + kap_a * pbar));
 #pragma unroll
-                for (int nu = 0; nu < L; ++nu) psi[(int64_t)(L + nu) * g.stride + idx] = cur.m[1][nu];
+                for (int nu = 0; nu < L; ++nu) ntst(&psi[(int64_t)(L + nu) * g.stride + idx], cur.m[1][nu]);
             }
         }
         if (PF) cur = nxt;
@@ -638,7 +638,7 @@ __global__ void __launch_bounds__(BX *BY) pressure_sweep3d(const StepArgs a, int
 #pragma unroll
             for (int ax = 0; ax < 3; ++ax)
 #pragma unroll
-                for (int nu = 0; nu < L; ++nu) o.m[ax][nu] = a.psi2[(int64_t)(ax * L + nu) * g.stride + idx];
+                for (int nu = 0; nu < L; ++nu) o.m[ax][nu] = ntld(&a.psi2[(int64_t)(ax * L + nu) * g.stride + idx]);
         }
     };
     Staged<XW, XH, NT> px;
@@ -729,7 +729,7 @@ __global__ void __launch_bounds__(BX *BY) pressure_sweep3d(const StepArgs a, int
 #pragma unroll
             for (int ax = 0; ax < 3; ++ax)
 #pragma unroll
-                for (int nu = 0; nu < L; ++nu) a.psi2[(int64_t)(ax * L + nu) * g.stride + idx] = m[ax][nu];
+                for (int nu = 0; nu < L; ++nu) ntst(&a.psi2[(int64_t)(ax * L + nu) * g.stride + idx], m[ax][nu]);
         }
     }
 }
@@ -784,7 +784,7 @@ __global__ void __launch_bounds__(BX *BY) velocity_sweep3d(const StepArgs a, int
 #pragma unroll
             for (int ax = 0; ax < 3; ++ax)
 #pragma unroll
-                for (int nu = 0; nu < L; ++nu) o.m[ax][nu] = a.psi1[(int64_t)(ax * L + nu) * g.stride + idx];
+                for (int nu = 0; nu < L; ++nu) o.m[ax][nu] = ntld(&a.psi1[(int64_t)(ax * L + nu) * g.stride + idx]);
         }
     };
     Staged<PW, PH, NT> ps;
@@ -883,7 +883,7 @@ __global__ void __launch_bounds__(BX *BY) velocity_sweep3d(const StepArgs a, int
                 }
                 a.v[(int64_t)ax * g.stride + idx] = u[ax] - a.dt * S / (rho_a * (1.0f + kap_a * pbar));
 #pragma unroll
-                for (int nu = 0; nu < L; ++nu) a.psi1[(int64_t)(ax * L + nu) * g.stride + idx] = m[ax][nu];
+                for (int nu = 0; nu < L; ++nu) ntst(&a.psi1[(int64_t)(ax * L + nu) * g.stride + idx], m[ax][nu]);
             }
         }
     }

@@ -15,6 +15,12 @@
 namespace fw2 {
 
 constexpr int kHalo = 4;
+
+// Memory variables are read and written once per step, by one kernel:
+// non-temporal accesses keep them from displacing the stencil fields that
+// the other kernel of the step reads back from cache.
+__device__ __forceinline__ float ntld(const float *p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ void ntst(float *p, float v) { __builtin_nontemporal_store(v, p); }
 constexpr int kMaxRelax = 4;
 
 struct Geometry {
