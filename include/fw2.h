@@ -39,7 +39,7 @@ typedef enum {
     FW2_E_UNSUPPORTED = 6   /* valid request this build does not implement */
 } fw2_status;
 
-#define FW2_MAX_RELAX 4     /* largest number of relaxation mechanisms L */
+#define FW2_MAX_RELAX 8     /* largest number of relaxation mechanisms L (batched stepping: 4) */
 #define FW2_MAX_LABELS 256  /* relaxation tuples addressable by a uint8 label */
 
 /* Field selection for fw2_read_fields / fw2_write_fields.  Selected fields

@@ -5,7 +5,7 @@ exponent y) from a small grid; each grid point needs a relaxation tuple that
 reproduces alpha0 f^y over 1-20 MHz (Sec. 4.1).  This script computes them
 once with the oracle's fitter and stores them as plain input data.
 
-    python -m oracle.make_tissue_fits [--jobs N]
+    python -m oracle.make_tissue_fits [--jobs N] [--missing]
 """
 import argparse
 import json
@@ -33,6 +33,9 @@ def wanted():
         for a0 in ALPHA0_GRID:
             for y in Y_GRID:
                 jobs.append((a0, y, L, 3e6))
+    for L in (5, 6, 7, 8):                # more mechanisms than the workloads use
+        jobs.append((1.5, 1.3, L, 3e6))
+        jobs.append((0.5, 1.0, L, 3e6))
     return jobs
 
 
@@ -45,10 +48,16 @@ def _one(job):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--jobs", type=int, default=os.cpu_count() or 1)
+    ap.add_argument("--missing", action="store_true", help="keep the stored fits, compute only absent ones")
     args = ap.parse_args()
     out = {}
+    jobs = wanted()
+    if args.missing and os.path.exists(OUT):
+        with open(OUT) as fh:
+            out = json.load(fh)["fits"]
+        jobs = [j for j in jobs if key(*j) not in out]
     with ProcessPoolExecutor(max_workers=args.jobs) as ex:
-        for k, v in ex.map(_one, wanted()):
+        for k, v in ex.map(_one, jobs):
             out[k] = v
             print(k, "att_err %.4f vel_err %.2e" % (v["max_att_err"], v["max_vel_err"]), flush=True)
     out = dict(sorted(out.items()))

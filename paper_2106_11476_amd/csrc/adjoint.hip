@@ -860,7 +860,7 @@ hipError_t launch_adjoint_step(const StepArgs &f, const SparseArgs &src, const S
         }
     }
 #endif
-    switch (f.geo.ndim * 8 + L) {
+    switch (f.geo.ndim * 8 + L) {            // L = 1..8
     case 2 * 8 + 1: return adjoint_step_points<2, 1>(f, src, rcv, state, state_prev, b, step, have_pp, residual, st, pp_next);
     case 2 * 8 + 2: return adjoint_step_points<2, 2>(f, src, rcv, state, state_prev, b, step, have_pp, residual, st, pp_next);
     case 2 * 8 + 3: return adjoint_step_points<2, 3>(f, src, rcv, state, state_prev, b, step, have_pp, residual, st, pp_next);
@@ -869,6 +869,14 @@ hipError_t launch_adjoint_step(const StepArgs &f, const SparseArgs &src, const S
     case 3 * 8 + 2: return adjoint_step_points<3, 2>(f, src, rcv, state, state_prev, b, step, have_pp, residual, st, pp_next);
     case 3 * 8 + 3: return adjoint_step_points<3, 3>(f, src, rcv, state, state_prev, b, step, have_pp, residual, st, pp_next);
     case 3 * 8 + 4: return adjoint_step_points<3, 4>(f, src, rcv, state, state_prev, b, step, have_pp, residual, st, pp_next);
+    case 2 * 8 + 5: return adjoint_step_points<2, 5>(f, src, rcv, state, state_prev, b, step, have_pp, residual, st, pp_next);
+    case 2 * 8 + 6: return adjoint_step_points<2, 6>(f, src, rcv, state, state_prev, b, step, have_pp, residual, st, pp_next);
+    case 2 * 8 + 7: return adjoint_step_points<2, 7>(f, src, rcv, state, state_prev, b, step, have_pp, residual, st, pp_next);
+    case 2 * 8 + 8: return adjoint_step_points<2, 8>(f, src, rcv, state, state_prev, b, step, have_pp, residual, st, pp_next);
+    case 3 * 8 + 5: return adjoint_step_points<3, 5>(f, src, rcv, state, state_prev, b, step, have_pp, residual, st, pp_next);
+    case 3 * 8 + 6: return adjoint_step_points<3, 6>(f, src, rcv, state, state_prev, b, step, have_pp, residual, st, pp_next);
+    case 3 * 8 + 7: return adjoint_step_points<3, 7>(f, src, rcv, state, state_prev, b, step, have_pp, residual, st, pp_next);
+    case 3 * 8 + 8: return adjoint_step_points<3, 8>(f, src, rcv, state, state_prev, b, step, have_pp, residual, st, pp_next);
     default: return hipErrorInvalidValue;
     }
 }

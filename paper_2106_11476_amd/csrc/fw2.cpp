@@ -889,6 +889,7 @@ fw2_status fw2_batch_set_domains(fw2_batch *b, int32_t n, fw2_domain *const *dom
         if (d->desc.ndim != 2) return fail(FW2_E_UNSUPPORTED, "batched stepping is 2D only");
         if (d->desc.stencil_mode != FW2_STENCIL_GLOBAL)
             return fail(FW2_E_UNSUPPORTED, "batched stepping uses global stencil weights only");
+        if (d->desc.n_relax > 4) return fail(FW2_E_UNSUPPORTED, "batched stepping takes at most 4 mechanisms");
         if (d->step >= n_steps[k]) return fail(FW2_E_INVALID, "domain already at or past its n_steps");
         for (int32_t q = 0; q < k; ++q)
             if (domains[q] == d) return fail(FW2_E_INVALID, "domain listed twice");

@@ -948,6 +948,7 @@ hipError_t launch_sweep(const StepArgs &a, bool pressure, const KernelConfig &kc
     const int nby = (a.geo.n[1] + kc.rows - 1) / kc.rows;
     const int nblocks = nbx * nby;
 #define FW2_SWEEP(BXV)                                                                                  \
+    if constexpr (L <= 4 || BXV == 256)                                                                 \
     if (kc.bx == BXV) {                                                                                 \
         if (pressure)                                                                                   \
             hipLaunchKernelGGL((pressure_sweep2d<L, C, BXV, PF, PP>), dim3(nblocks), dim3(BXV), 0, st, a, kc.rows, nbx, nblocks); \
@@ -966,6 +967,7 @@ template <int L, bool C, bool PP, bool PF>
 hipError_t launch_sweep3(const StepArgs &a, bool pressure, const KernelConfig &kc, hipStream_t st)
 {
 #define FW2_SWEEP3(BXV, BYV)                                                                            \
+    if constexpr (L <= 4 || (BXV == 64 && BYV == 8))                                                    \
     if (kc.bx == BXV) {                                                                                 \
         const int nbx = (a.geo.n[0] + BXV - 1) / BXV, nby = (a.geo.n[1] + BYV - 1) / BYV;                \
         const int nbz = (a.geo.n[2] + kc.rows - 1) / kc.rows;                                           \
@@ -1108,11 +1110,21 @@ hipError_t launch_v(const StepArgs &a, hipStream_t st)
 template <bool P, int NDIM, int L, bool C, bool PP>
 hipError_t dispatch_variant(const StepArgs &a, const KernelConfig &kc, hipStream_t st)
 {
-    if (NDIM == 3 && kc.variant == 1) return launch_sweep3<L, C, PP, false>(a, P, kc, st);
-    if (NDIM == 3 && kc.variant == 2) return launch_sweep3<L, C, PP, true>(a, P, kc, st);
-    if (NDIM == 2 && kc.variant == 1) return launch_sweep<L, C, false, PP>(a, P, kc, st);
-    if (NDIM == 2 && kc.variant == 2) return launch_sweep<L, C, true, PP>(a, P, kc, st);
-    return P ? launch_p<NDIM, L, C, PP>(a, st) : launch_v<NDIM, L, C, PP>(a, st);
+    if constexpr (L > 4) {
+        // more than four mechanisms: the generic kernel, or one sweep shape per
+        // dimension (256-column 2D rows; 64 x 8 3D columns without the plane
+        // prefetch, whose second copy of the memory variables would not fit
+        // the registers)
+        if (kc.variant == 0) return P ? launch_p<NDIM, L, C, PP>(a, st) : launch_v<NDIM, L, C, PP>(a, st);
+        if (NDIM == 2) return launch_sweep<L, C, false, PP>(a, P, KernelConfig{1, 256, kc.rows}, st);
+        return launch_sweep3<L, C, PP, false>(a, P, KernelConfig{1, 64, kc.rows}, st);
+    } else {
+        if (NDIM == 3 && kc.variant == 1) return launch_sweep3<L, C, PP, false>(a, P, kc, st);
+        if (NDIM == 3 && kc.variant == 2) return launch_sweep3<L, C, PP, true>(a, P, kc, st);
+        if (NDIM == 2 && kc.variant == 1) return launch_sweep<L, C, false, PP>(a, P, kc, st);
+        if (NDIM == 2 && kc.variant == 2) return launch_sweep<L, C, true, PP>(a, P, kc, st);
+        return P ? launch_p<NDIM, L, C, PP>(a, st) : launch_v<NDIM, L, C, PP>(a, st);
+    }
 }
 
 template <bool P, int NDIM, int L>
@@ -1132,6 +1144,10 @@ hipError_t dispatch_L(const StepArgs &a, int L, int scheme, const KernelConfig &
     case 2: return dispatch_scheme<P, NDIM, 2>(a, scheme, kc, st);
     case 3: return dispatch_scheme<P, NDIM, 3>(a, scheme, kc, st);
     case 4: return dispatch_scheme<P, NDIM, 4>(a, scheme, kc, st);
+    case 5: return dispatch_scheme<P, NDIM, 5>(a, scheme, kc, st);
+    case 6: return dispatch_scheme<P, NDIM, 6>(a, scheme, kc, st);
+    case 7: return dispatch_scheme<P, NDIM, 7>(a, scheme, kc, st);
+    case 8: return dispatch_scheme<P, NDIM, 8>(a, scheme, kc, st);
     default: return hipErrorInvalidValue;
     }
 }

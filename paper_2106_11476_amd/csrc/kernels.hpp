@@ -21,7 +21,6 @@ constexpr int kHalo = 4;
 // the other kernel of the step reads back from cache.
 __device__ __forceinline__ float ntld(const float *p) { return __builtin_nontemporal_load(p); }
 __device__ __forceinline__ void ntst(float *p, float v) { __builtin_nontemporal_store(v, p); }
-constexpr int kMaxRelax = 4;
 
 struct Geometry {
     int32_t ndim;

@@ -50,7 +50,7 @@ def test_workspace_bytes_counts_every_array():
 @pytest.mark.parametrize("mutate,msg", [
     (lambda p: setattr(p, "bound_cells", (300, 48)), "wider"),
     (lambda p: setattr(p, "trans_cells", (60, 30)), "trans_cells"),
-    (lambda p: setattr(p, "n_relax", 5), "n_relax"),
+    (lambda p: setattr(p, "n_relax", 9), "n_relax"),
     (lambda p: setattr(p, "dt", -1.0), "positive"),
     (lambda p: setattr(p, "pml_Rc", 1.5), "pml_Rc"),
     (lambda p: setattr(p, "relax_scheme", 3), "relax_scheme"),

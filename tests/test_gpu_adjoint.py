@@ -82,7 +82,8 @@ def _rel_l2(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
-@pytest.mark.parametrize("shape,L,seed,n", [((70, 45), 2, 3, 110), ((131, 37), 3, 5, 90), ((66, 40), 1, 4, 100)])
+@pytest.mark.parametrize("shape,L,seed,n", [((70, 45), 2, 3, 110), ((131, 37), 3, 5, 90), ((66, 40), 1, 4, 100),
+                                              ((60, 44), 6, 6, 90)])
 def test_gradient_matches_oracle_adjoint_2d(shape, L, seed, n):
     prob = _problem(shape, L, seed, n)
     obs = _obs(prob, n)

@@ -123,3 +123,17 @@ def test_autotuner_picks_a_candidate():
     cands = ((256, 4), (64, 8))
     best, t = serve.autotune_tile(probs, candidates=cands, steps=16)
     assert best in cands and all(v > 0 for v in t.values())
+
+
+def test_batch_refuses_more_than_four_mechanisms():
+    torch = _torch()
+    from paper_2106_11476_amd import fw2
+    prob = W.random_medium((40, 36), 5, 2, seed=3, nb=4, ntr=2)
+    _say("batch refuses L = 5")
+    dom = fw2.Domain(prob, device="cuda:0")
+    batch = fw2.Batch(max_domains=2, device="cuda:0")
+    with pytest.raises(fw2.Fw2Error, match="UNSUPPORTED"):
+        batch.set_domains([dom], [10])
+    torch.cuda.synchronize()
+    batch.destroy()
+    dom.destroy_domain()

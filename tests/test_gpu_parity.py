@@ -325,3 +325,36 @@ def test_kernel_variants_match_oracle(monkeypatch, config, shape, L, scheme):
     f, tr, _ = gpu_run(prob, 12, state=st)
     ref, rtr = oracle_run(prob, 12, state=st)
     compare(f, tr, ref, rtr, "variant %s %s" % (config, shape), prob=prob)
+
+
+# ------------------------------------------------- more than four mechanisms ---
+
+@pytest.mark.parametrize("config", [None, "0,64,16"])
+@pytest.mark.parametrize("shape,L,scheme", [((70, 45), 5, 1), ((131, 40), 6, 0), ((64, 48), 8, 1),
+                                            ((19, 17, 15), 6, 1), ((21, 18, 13), 8, 0)])
+def test_many_mechanisms_match_oracle(monkeypatch, config, shape, L, scheme):
+    """L = 5..8 (fitted tuples) in 2D and 3D, both memory schemes, default
+    sweep kernels and the generic kernel."""
+    if config:
+        monkeypatch.setenv("FW2_KERNEL_CONFIG", config if len(shape) == 2 else "0,32,16")
+    prob = W.random_medium(shape, L, 2, seed=L + len(shape), nb=5, ntr=3)
+    prob.relax_scheme = scheme
+    st = _state(prob, 29)
+    _say("mechanisms", L, shape, "scheme", scheme, "config", config)
+    f, tr, _ = gpu_run(prob, 10, state=st)
+    ref, rtr = oracle_run(prob, 10, state=st)
+    compare(f, tr, ref, rtr, "L=%d %s" % (L, shape), prob=prob)
+
+
+def test_many_mechanisms_point_source_run():
+    """A 2D pulse through a medium fitted with six mechanisms, 400 steps."""
+    prob = W.random_medium((96, 80), 6, 2, seed=31, nb=10, ntr=6)
+    prob.src_idx = prob.flat(np.array([48]), np.array([40]))
+    prob.src_sig = np.zeros(1, np.int32)
+    prob.src_w = np.ones(1, np.float32)
+    prob.signals = W.gaussian_pulse(400, prob.dt, 3e6, 3, 1e5)[None]
+    prob.rcv_idx = prob.flat(np.array([10, 80]), np.array([15, 60]))
+    _say("six mechanisms, point source, 400 steps")
+    f, tr, _ = gpu_run(prob, 400)
+    ref, rtr = oracle_run(prob, 400)
+    compare(f, tr, ref, rtr, "L=6 point source", prob=prob)

@@ -117,15 +117,20 @@ def test_attenuation_and_dispersion_follow_power_law(oracle_lib):
         assert abs(vel / physics.kk_phase_velocity(fk, 0.5, 1.0, C0, 2e6) - 1) < 0.005
 
 
-def test_attenuation_y_not_one_and_four_mechanisms(oracle_lib):
+@pytest.mark.parametrize("L", [4, 6, 8])
+def test_attenuation_y_not_one_and_many_mechanisms(oracle_lib, L):
     """Same measurement for a y = 1.3 law with four mechanisms (the kind of
-    tuple the heterogeneous 2D workload uses) at 3 and 12 MHz."""
-    row = W.tissue_row(1.5, 1.3, 4, 3e6)
+    tuple the heterogeneous 2D workload uses) and with six and eight, at 3
+    and 12 MHz.  Phase velocity: within 2e-4 of the dispersion relation with
+    four mechanisms, 3e-4 with six and eight (measured 2.0e-4 and 2.2e-4 at
+    12 MHz), in all cases more than an order of magnitude inside the
+    paper's 0.5 %."""
+    row = W.tissue_row(1.5, 1.3, L, 3e6)
     for f0 in (3e6, 12e6):
-        fk, att, vel = _plane_wave_measure(row, 4, f0)
-        a_an, c_an = relaxation.model_attenuation_velocity(np.array([fk]), C0, np.array(row), 4)
+        fk, att, vel = _plane_wave_measure(row, L, f0)
+        a_an, c_an = relaxation.model_attenuation_velocity(np.array([fk]), C0, np.array(row), L)
         assert abs(att / a_an[0] - 1) < 0.01
-        assert abs(vel / c_an[0] - 1) < 2e-4
+        assert abs(vel / c_an[0] - 1) < (2e-4 if L <= 4 else 3e-4)
         assert abs(att / physics.power_law_db_cm(fk, 1.5, 1.3) - 1) < 0.05
 
 

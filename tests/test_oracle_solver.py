@@ -33,7 +33,7 @@ def _random_state(prob, seed):
     return st
 
 
-@pytest.mark.parametrize("shape,L", [((37, 29), 2), ((23, 19), 4), ((13, 11, 9), 2), ((12, 10, 9), 1)])
+@pytest.mark.parametrize("shape,L", [((37, 29), 2), ((23, 19), 4), ((13, 11, 9), 2), ((12, 10, 9), 1), ((21, 17), 7)])
 def test_c_stepper_matches_numpy_twin(oracle_lib, shape, L):
     """Two independent codings of the same steps (plain loops with explicit
     bounds checks vs. whole-array shifts of a zero-padded field) agree."""

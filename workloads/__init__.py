@@ -160,7 +160,12 @@ def random_medium(shape, L, n_labels, seed, nb=8, ntr=6, ppw=12, f0=3e6, cfl=0.4
     for k in range(n_labels):
         a0 = ALPHA0_GRID[rng.integers(len(ALPHA0_GRID))]
         y = Y_GRID[rng.integers(len(Y_GRID))]
-        rows.append(tissue_row(a0, y, L, 3e6) if L in (2, 3, 4) else lossless_row(L))
+        if L in (2, 3, 4):
+            rows.append(tissue_row(a0, y, L, 3e6))
+        elif 5 <= L <= 8:                    # fits stored for two tissues only
+            rows.append(tissue_row(*((1.5, 1.3) if k % 2 == 0 else (0.5, 1.0)), L, 3e6))
+        else:
+            rows.append(lossless_row(L))
     label = rng.integers(0, n_labels, grid).astype(np.uint8)
     return Problem(shape=tuple(shape), h=h, dt=dt, n_relax=L, c=c, rho=rho, beta=beta,
                    relax_table=np.asarray(rows, np.float64), label=label,
