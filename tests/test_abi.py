@@ -76,3 +76,22 @@ def test_null_arguments_are_rejected_without_a_gpu():
     h = ctypes.c_void_p()
     assert lib.fw2_create_domain(ctypes.byref(d), None, 0, ctypes.byref(h)) == 1
     assert b"workspace" in lib.fw2_last_error()
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    """Without the built HIP library the binding raises; there is no CPU
+    fallback of any step."""
+    monkeypatch.setattr(fw2, "LIB_PATH", str(tmp_path / "libfw2.so"))
+    monkeypatch.setattr(fw2, "_lib", None)
+    with pytest.raises(RuntimeError, match="not built"):
+        fw2.lib()
+
+
+def test_product_package_does_not_import_the_oracle():
+    """The oracle is test infrastructure: no module of the package refers to it."""
+    pkg = os.path.join(ROOT, "paper_2106_11476_amd")
+    for name in os.listdir(pkg):
+        if name.endswith(".py"):
+            src = open(os.path.join(pkg, name)).read()
+            assert not re.search(r"^\s*(from|import)\s+oracle\b", src, re.M), name
+            assert "from oracle" not in src and "import oracle" not in src, name
