@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <vector>
 
 namespace fw2 {
 
@@ -64,23 +65,32 @@ void stencil_polynomials(int ndim, double pw[4][4], double *g11_per_s)
 
 double stability_factor(double r, int ndim, const double g[4], double g11)
 {
+    // The symbol of one axis depends only on that axis' wavenumber, so the
+    // sines and cosines are tabulated once per sample (M of them) and the
+    // sweep over the M^ndim wavenumber grid is arithmetic only.
     const int M = ndim == 2 ? 181 : 61;
     const double pi = 3.14159265358979323846;
+    std::vector<double> ax(M), sh(M), co(M);
+    for (int i = 0; i < M; ++i) {
+        const double th = pi * i / (M - 1);
+        double A = 0.0;
+        for (int m = 1; m <= 4; ++m) A += g[m - 1] * std::sin((2 * m - 1) * th / 2.0);
+        ax[i] = A;
+        sh[i] = std::sin(th / 2.0);
+        co[i] = std::cos(th);
+    }
     double worst = 0.0;
     int cnt[3] = {M, M, ndim == 3 ? M : 1};
     for (int iz = 0; iz < cnt[2]; ++iz)
         for (int iy = 0; iy < cnt[1]; ++iy)
             for (int ix = 0; ix < cnt[0]; ++ix) {
-                const double th[3] = {pi * ix / (M - 1), pi * iy / (M - 1),
-                                      ndim == 3 ? pi * iz / (M - 1) : 0.0};
+                const int id[3] = {ix, iy, iz};
                 double s2 = 0.0;
                 for (int a = 0; a < ndim; ++a) {
-                    double A = 0.0;
-                    for (int m = 1; m <= 4; ++m) A += g[m - 1] * std::sin((2 * m - 1) * th[a] / 2.0);
                     double cs = 0.0;
                     for (int b = 0; b < ndim; ++b)
-                        if (b != a) cs += std::cos(th[b]);
-                    A += 2.0 * g11 * std::sin(th[a] / 2.0) * cs;
+                        if (b != a) cs += co[id[b]];
+                    const double A = ax[id[a]] + 2.0 * g11 * sh[id[a]] * cs;
                     s2 += A * A;
                 }
                 worst = std::max(worst, r * std::sqrt(s2));
