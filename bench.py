@@ -29,13 +29,40 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, 8 TB/s
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2106_11476_amd", "csrc", "kernels.hip")
+ADJOINT_SOURCE = os.path.join(ROOT, "paper_2106_11476_amd", "csrc", "adjoint.hip")
+ADJOINT_WORKLOAD = "inversion_2d_1536"
 PROFILES = os.path.join(ROOT, "profiles")
 
 
-def kernel_source_sha():
+def kernel_source_sha(path=KERNEL_SOURCE):
     import hashlib
-    with open(KERNEL_SOURCE, "rb") as fh:
+    with open(path, "rb") as fh:
         return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def _profile_values(path):
+    vals = {}
+    for line in open(path):
+        if ":" in line and not line.startswith(" "):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    return vals
+
+
+def measured_adjoint_traffic():
+    """HBM bytes per point of one reverse step (both kernels, sparse ones
+    included) from the committed counter summary, or None when there is none
+    or the adjoint kernels changed since the counters were taken."""
+    path = os.path.join(PROFILES, "traffic_adjoint_step_%s.txt" % ADJOINT_WORKLOAD)
+    if not os.path.exists(path):
+        return None
+    vals = _profile_values(path)
+    if vals.get("adjoint_source_sha256_16") != kernel_source_sha(ADJOINT_SOURCE):
+        return None
+    try:
+        return float(vals["hbm_bytes_per_point_reverse_step"])
+    except (KeyError, ValueError):
+        return None
 
 
 def measured_traffic(kernel, workload):
@@ -45,11 +72,7 @@ def measured_traffic(kernel, workload):
     path = os.path.join(PROFILES, "traffic_%s_%s.txt" % (kernel, workload))
     if not os.path.exists(path):
         return None
-    vals = {}
-    for line in open(path):
-        if ":" in line and not line.startswith(" "):
-            k, v = line.split(":", 1)
-            vals[k.strip()] = v.strip()
+    vals = _profile_values(path)
     if vals.get("kernel_source_sha256_16") != kernel_source_sha():
         return None
     try:
@@ -273,7 +296,8 @@ def adjoint_leg(steps=6000, K=64, shot=31, timed_reverse=200):
             "reverse_step_ms": round(ms, 5),
             "reverse_gpts": round(prob.npts / (ms * 1e-3) / 1e9, 3),
             "reverse_roofline": {"bound": "hbm", "alg_bytes_per_point": b, "achieved": round(gbs, 1),
-                                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4)}}
+                                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+                                 "traffic_bytes_per_point": measured_adjoint_traffic()}}
 
 
 def _db_rows(db, sql):
@@ -358,7 +382,64 @@ def summarize_profiles(stats_db, fetch_db, write_db, workload, copy_bytes, comma
     print("profiles written to", PROFILES)
 
 
+def summarize_adjoint(stats_db, fetch_db, write_db, copy_bytes, commands):
+    """Write the kernel statistics and the per-kernel traffic of the adjoint
+    leg (FETCH_SIZE / WRITE_SIZE passes, KiB per dispatch, scaled by what the
+    counters read for the plain copy of copy_bytes)."""
+    stats = _db_rows(stats_db, "select name, total_calls, total_duration, average from top_kernels")
+    fetch = _db_rows(fetch_db, "select name, avg(counter_value), max(counter_value), count(*) from pmc_events group by name")
+    write = _db_rows(write_db, "select name, avg(counter_value), max(counter_value), count(*) from pmc_events group by name")
+    fmax = {r[0]: r for r in fetch}
+    wmax = {r[0]: r for r in write}
+    copy_name = "__amd_rocclr_copyBuffer"
+    f_scale = copy_bytes / 1024.0 / fmax[copy_name][2]
+    w_scale = copy_bytes / 1024.0 / wmax[copy_name][2]
+    sha = kernel_source_sha(ADJOINT_SOURCE)
+    npts = 1536 * 1536
+    os.makedirs(PROFILES, exist_ok=True)
+    lines = ["rocprofv3 kernel statistics: adjoint leg of the benchmark: one shot of the 1536^2 inversion "
+             "workload (forward with checkpoints, segment recompute and reverse-step kernels)", "commands:"]
+    lines += ["  " + c for c in commands]
+    lines.append("adjoint_source_sha256_16: %s" % sha)
+    lines.append("%-70s %8s %12s %10s" % ("kernel", "calls", "total_us", "avg_us"))
+    for name, calls, tot, avg in stats:
+        lines.append("%-70s %8d %12.1f %10.3f" % (name[:70], calls, tot, avg))
+    with open(os.path.join(PROFILES, "kernel_stats_%s_adjoint.txt" % ADJOINT_WORKLOAD), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    # the steady reverse step: velocity kernel (deferred A3), receivers,
+    # pressure kernel with the fused A0 of the step before, sources
+    parts = [("velocity", "adj_velocity<2, 2, true>"), ("pressure", "adj_pressure<2, 2, true>"),
+             ("receivers", "adj_receivers("), ("sources", "adj_sources(")]
+    txt = ["HBM traffic of one reverse step of the adjoint (2D, L = 2) on the 1536^2 inversion workload",
+           "commands:"] + ["  " + c for c in commands]
+    txt += ["adjoint_source_sha256_16: %s" % sha, "points: %d" % npts, "copy_probe_bytes: %d" % copy_bytes,
+            "fetch_scale: %.4f" % f_scale, "write_scale: %.4f" % w_scale]
+    total = 0.0
+    for short, key in parts:
+        names = [n for n in fmax if key in n]
+        if not names:
+            continue
+        n = names[0]
+        fk, wk = fmax[n][1], wmax[n][1]
+        b = (fk * f_scale + wk * w_scale) * 1024.0
+        total += b
+        avg_us = [r[3] for r in stats if r[0] == n]
+        txt += ["%s_kernel: %s" % (short, n),
+                "%s_fetch_kib_per_dispatch_raw: %.1f" % (short, fk),
+                "%s_write_kib_per_dispatch_raw: %.1f" % (short, wk),
+                "%s_hbm_bytes_per_point: %.2f" % (short, b / npts),
+                "%s_avg_duration_us_kernel_trace: %s" % (short, ("%.3f" % avg_us[0]) if avg_us else "n/a")]
+    alg = adjoint_bytes(2, 2, True)
+    txt += ["hbm_bytes_per_point_reverse_step: %.2f" % (total / npts),
+            "algorithmic_bytes_per_point_reverse_step: %d" % alg,
+            "traffic_over_algorithmic: %.4f" % (total / npts / alg)]
+    with open(os.path.join(PROFILES, "traffic_adjoint_step_%s.txt" % ADJOINT_WORKLOAD), "w") as fh:
+        fh.write("\n".join(txt) + "\n")
+    print("profiles written to", PROFILES)
+
+
 def main():
+    global PROFILES
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=12000)
@@ -381,7 +462,14 @@ def main():
     ap.add_argument("--commands", nargs="*", default=[])
     ap.add_argument("--summarize-stats", nargs=3, metavar=("STATS_DB", "NAME", "TITLE"),
                     help="write profiles/kernel_stats_NAME.txt from one kernel-trace database and exit")
+    ap.add_argument("--summarize-adjoint", nargs=3, metavar=("STATS_DB", "FETCH_DB", "WRITE_DB"),
+                    help="write the adjoint leg's kernel statistics and traffic summaries and exit")
+    ap.add_argument("--profiles-dir", default=PROFILES, help="where the summaries go")
     args = ap.parse_args()
+    PROFILES = args.profiles_dir
+    if args.summarize_adjoint:
+        summarize_adjoint(*args.summarize_adjoint, copy_bytes=args.copy_read_bytes, commands=args.commands)
+        return
     if args.summarize_stats:
         summarize_stats_only(*args.summarize_stats, commands=args.commands)
         return

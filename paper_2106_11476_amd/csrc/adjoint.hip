@@ -67,7 +67,19 @@ struct AdjArgs {
     float *lkv;              // [ndim] adjoint of kappa0_a
     float *lDp;              // [ndim] adjoint of D^- v_a at p points
     float *gk;               // dJ/dkappa0
+    int nbx, nby, nblocks;   // blocks along x and y; blocks in the 1D launch
 };
+
+// Point block of a 1D launch.  Blocks are dealt to the 8 XCDs round-robin
+// (block b runs on XCD b mod 8); renumbering them so that XCD x takes one
+// contiguous run of point blocks keeps the stencil rows that neighbouring
+// blocks share in that XCD's L2 instead of fetching them once per XCD.
+// A bijection of [0, nblocks) for any nblocks.
+__device__ __forceinline__ int xcd_block(int bid, int nblocks)
+{
+    const int x = bid % 8, q = nblocks / 8, rem = nblocks % 8;
+    return x * q + min(x, rem) + bid / 8;
+}
 
 __device__ __forceinline__ int64_t aoff(const Geometry &g, int a)
 {
@@ -113,9 +125,11 @@ __device__ __forceinline__ int slot_v(int x, int n, int nb) { return max(max(nb 
 
 #define ADJ_POINT                                                                  \
     const Geometry &g = A.f.geo;                                                   \
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;                           \
-    const int j = blockIdx.y * blockDim.y + threadIdx.y;                           \
-    const int k = blockIdx.z;                                                      \
+    const int blk = xcd_block(blockIdx.x, A.nblocks);                              \
+    const int bxy = blk % (A.nbx * A.nby);                                         \
+    const int i = (bxy % A.nbx) * blockDim.x + threadIdx.x;                        \
+    const int j = (bxy / A.nbx) * blockDim.y + threadIdx.y;                        \
+    const int k = blk / (A.nbx * A.nby);                                           \
     if (i >= g.n[0] || j >= g.n[1]) return;                                        \
     const int c3[3] = {i, j, k};                                                   \
     const int64_t idx = g.origin + (int64_t)k * g.plane + (int64_t)j * g.pitch + i; \
@@ -788,6 +802,17 @@ hipError_t adjoint_step_2d(AdjSweep A, const SparseArgs &src, const float *state
 
 namespace {
 
+// Sets the block counts of a 1D launch of point blocks of the given shape
+// over the grid (z planes of one block each) and returns the block count.
+unsigned point_grid(AdjArgs &A, dim3 block)
+{
+    const Geometry &g = A.f.geo;
+    A.nbx = (g.n[0] + (int)block.x - 1) / (int)block.x;
+    A.nby = (g.n[1] + (int)block.y - 1) / (int)block.y;
+    A.nblocks = A.nbx * A.nby * g.n[2];
+    return (unsigned)A.nblocks;
+}
+
 // One thread per point.  A3 of each step is deferred into the velocity
 // kernel of the next call; A0 of the step before is fused into the pressure
 // kernel when its state is given, else run at the start of the next call.
@@ -808,9 +833,8 @@ hipError_t adjoint_step_points(const StepArgs &f, const SparseArgs &src, const S
     A.lkv = b.lkv;
     A.lDp = b.lDp;
     A.gk = b.gk;
-    const Geometry &g = f.geo;
     const dim3 block = adj_block();
-    const dim3 grid((g.n[0] + block.x - 1) / block.x, (g.n[1] + block.y - 1) / block.y, g.n[2]);
+    const dim3 grid(point_grid(A, block));
     if (!have_pp) {
         hipLaunchKernelGGL((adj_forward_p<ND, L>), grid, block, 0, st, A);
         if (src.n > 0 && step < src.n_t)
@@ -888,9 +912,8 @@ hipError_t launch_adjoint_gradient(const StepArgs &f, const AdjointBuffers &b, h
     std::memset(&A, 0, sizeof(A));
     A.f = f;
     A.gk = b.gk;
-    const Geometry &g = f.geo;
     const dim3 block = adj_block();
-    const dim3 grid((g.n[0] + block.x - 1) / block.x, (g.n[1] + block.y - 1) / block.y, g.n[2]);
+    const dim3 grid(point_grid(A, block));
     hipLaunchKernelGGL(adj_grad_c, grid, block, 0, st, A, b.out);
     return hipGetLastError();
 }
