@@ -21,9 +21,9 @@
 //   A3  v points inside the grid: lam_v_a -= D^+(lam_D_a)
 // using (D^-)^T = -(D^+) and (D^+)^T = -(D^-).
 // The phases run as one-thread-per-point kernels, two per step: A3 of a step
-// is deferred into the velocity kernel (A1) of the next call, and A0 of the
-// step before is fused into the pressure kernel (A2) when its state is at
-// hand.  A 2D variant as two row sweeps per step is kept below behind a
+// is deferred into the velocity kernel (A1) of the next call, A_rcv runs in
+// extra blocks of that kernel, and A0 of the step before is fused into the
+// pressure kernel (A2) when its state is at hand.  A 2D variant as two row sweeps per step is kept below behind a
 // compile-time switch.
 #include "kernels.hpp"
 
@@ -67,7 +67,10 @@ struct AdjArgs {
     float *lkv;              // [ndim] adjoint of kappa0_a
     float *lDp;              // [ndim] adjoint of D^- v_a at p points
     float *gk;               // dJ/dkappa0
-    int nbx, nby, nblocks;   // blocks along x and y; blocks in the 1D launch
+    int nbx, nby, nblocks;   // blocks along x and y; point blocks in the 1D launch
+    const int64_t *rcv_idx;  // receivers (flat indices), added into lam_p by the
+    const float *residual;   // velocity kernel's extra blocks: trace - obs of this step
+    int n_rcv;               // 0: no receiver blocks
 };
 
 // Point block of a 1D launch.  Blocks are dealt to the 8 XCDs round-robin
@@ -179,10 +182,18 @@ __global__ void adj_sources(float *pp, const SparseArgs s, long long step)
 
 // A1: velocity phase reversed at v points.  DEFER_A3: first apply the A3 of
 // the step after (lam_v -= D^+ lam_Dp, lam_Dp left by the previous call).
+// Blocks past the point blocks add the receiver residual into lam_p (A_rcv),
+// which this kernel neither reads nor writes otherwise.
 template <int ND, int L, bool DEFER_A3>
 __global__ void __launch_bounds__(kABX *kABY) adj_velocity(const AdjArgs A)
 {
     constexpr int nd = ND;
+    if ((int)blockIdx.x >= A.nblocks) {
+        const int q = ((int)blockIdx.x - A.nblocks) * (int)(blockDim.x * blockDim.y) +
+                      (int)(threadIdx.y * blockDim.x + threadIdx.x);
+        if (q < A.n_rcv) atomicAdd(&A.lp[pidx(A.f.geo, A.rcv_idx[q])], A.residual[q]);
+        return;
+    }
     ADJ_POINT
     const int64_t st = g.stride;
     const float *m1 = A.sp + (int64_t)(1 + nd) * st;
@@ -229,13 +240,6 @@ __global__ void __launch_bounds__(kABX *kABY) adj_velocity(const AdjArgs A)
         opb[idx] = lQ * rho_a * kap_a;
         okv[idx] = lQ * rho_a * pbar;
     }
-}
-
-__global__ void adj_receivers(float *lp, const SparseArgs r, const float *__restrict__ residual)
-{
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= r.n) return;
-    atomicAdd(&lp[pidx(r.geo, r.idx[q])], residual[q]);
 }
 
 // A2: gather of the velocity-phase adjoints, then the pressure phase reversed.
@@ -835,14 +839,17 @@ hipError_t adjoint_step_points(const StepArgs &f, const SparseArgs &src, const S
     A.gk = b.gk;
     const dim3 block = adj_block();
     const dim3 grid(point_grid(A, block));
+    A.rcv_idx = rcv.idx;
+    A.residual = residual;
+    A.n_rcv = residual ? rcv.n : 0;
+    const unsigned nt = block.x * block.y;
+    const dim3 vgrid(grid.x + (unsigned)((A.n_rcv + (int)nt - 1) / (int)nt));
     if (!have_pp) {
         hipLaunchKernelGGL((adj_forward_p<ND, L>), grid, block, 0, st, A);
         if (src.n > 0 && step < src.n_t)
             hipLaunchKernelGGL(adj_sources, dim3((src.n + 255) / 256), dim3(256), 0, st, b.pp, src, step);
     }
-    hipLaunchKernelGGL((adj_velocity<ND, L, true>), grid, block, 0, st, A);
-    if (rcv.n > 0 && residual)
-        hipLaunchKernelGGL(adj_receivers, dim3((rcv.n + 255) / 256), dim3(256), 0, st, b.lp, rcv, residual);
+    hipLaunchKernelGGL((adj_velocity<ND, L, true>), vgrid, block, 0, st, A);
     if (state_prev && step >= 1) {
         hipLaunchKernelGGL((adj_pressure<ND, L, true>), grid, block, 0, st, A);
         if (src.n > 0 && step - 1 < src.n_t)
