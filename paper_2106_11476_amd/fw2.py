@@ -301,12 +301,34 @@ class Domain:
             o += k
         return out
 
+    def field_numel(self, mask=FIELD_ALL):
+        """Elements of the packed layout of the selected fields."""
+        return sum(int(np.prod(s)) for _, s in self._sizes(mask))
+
     def read_fields_device(self, mask=FIELD_ALL):
         """Selected fields packed into one torch device tensor."""
-        total = sum(int(np.prod(s)) for _, s in self._sizes(mask))
+        total = self.field_numel(mask)
         buf = self.torch.empty(total, dtype=self.torch.float32, device=self.device)
         _check(lib().fw2_read_fields(self._h, mask, ctypes.c_void_p(buf.data_ptr()), DEVICE))
         return buf
+
+    def write_fields_device(self, buf, mask=FIELD_ALL):
+        """Write the selected fields from one packed torch device tensor (the
+        layout read_fields_device returns)."""
+        total = self.field_numel(mask)
+        if buf.numel() != total or buf.dtype != self.torch.float32 or not buf.is_contiguous():
+            raise ValueError("expected a contiguous float32 tensor of %d elements" % total)
+        self.torch.cuda.current_stream(self.device).synchronize()
+        _check(lib().fw2_write_fields(self._h, mask, ctypes.c_void_p(buf.data_ptr()), DEVICE))
+
+    def field_views(self, buf, mask=FIELD_ALL):
+        """{name: view} of a packed field tensor (host or device)."""
+        out, o = {}, 0
+        for name, s in self._sizes(mask):
+            k = int(np.prod(s))
+            out[name] = buf[o:o + k].reshape(s)
+            o += k
+        return out
 
     def write_fields(self, fields, mask=None):
         """fields: dict name -> array (names as read_fields returns)."""

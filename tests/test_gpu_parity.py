@@ -185,6 +185,86 @@ def test_skull_3d_small_cube():
     compare(f, tr, ref, rtr, "skull_3d_96", prob=prob)
 
 
+def test_skull_3d_full_size_window():
+    """The 1024^3 grid of the transcranial workload in the benchmark's launch
+    configuration (plane-prefetch sweeps over 64 x 8 columns, 64 planes per
+    block, graph-captured steps), checked where the oracle can follow it: a
+    96^3 window at the centre holds a heterogeneous two-tissue medium (c
+    1540-3080, the workload's two relaxation tuples, layers 48 cells thick as
+    in the workload), the rest is the brain-like background, and a seeded
+    random state fills a 16^3 block in the middle of the window.  One step
+    moves information at most 8 cells along an axis, so after 3 steps every
+    nonzero sample lies within 28 cells of the block, inside the window's
+    interior.  The same window as its own 96^3 grid (same h, dt, stencil r and
+    layer constants; 6-cell layers outside that reach) run by the oracle must
+    give the same fields over the whole window."""
+    torch = _torch()
+    from paper_2106_11476_amd import fw2
+    N, n, blk, steps = 1024, 96, 16, 3
+    h = W.grid_spacing(1540.0, 1e6, 12)
+    c_max = 3080.0
+    dt = 0.4 * h / c_max
+    rows = np.asarray([W.TABLE2_ROW, W.tissue_row(8.0, 1.0, 2, 1e6)], np.float64)
+    rng = np.random.default_rng(1024)
+    wc = rng.uniform(1540.0, c_max, (n, n, n)).astype(np.float32)
+    wr = (1040.0 + (wc - 1540.0) * (860.0 / 1540.0)).astype(np.float32)
+    wb = rng.uniform(3.5, 5.5, (n, n, n)).astype(np.float32)
+    wl = (wc > 2300.0).astype(np.uint8)
+
+    def problem(size, nb, ntr):
+        grid = (size,) * 3
+        return W.Problem(shape=grid, h=h, dt=dt, n_relax=2, c=np.full(grid, 1540.0, np.float32),
+                         rho=np.full(grid, 1040.0, np.float32), beta=np.full(grid, 4.0, np.float32),
+                         relax_table=rows, label=np.zeros(grid, np.uint8), bound_cells=(nb,) * 3,
+                         trans_cells=(ntr,) * 3, pml_cp=c_max, fd_r=c_max * dt / h, n_steps=steps)
+
+    small = problem(n, 6, 4)
+    small.c[...], small.rho[...], small.beta[...], small.label[...] = wc, wr, wb, wl
+    st = {"p": np.zeros((n, n, n), np.float32), "v": np.zeros((3, n, n, n), np.float32),
+          "psi1": np.zeros((3, 2, n, n, n), np.float32), "psi2": np.zeros((3, 2, n, n, n), np.float32)}
+    b0 = (n - blk) // 2
+    inner = (slice(b0, b0 + blk),) * 3
+    for name, arr in zip(("p", "v", "psi1", "psi2"), W.random_state(3, 2, (blk,) * 3, 77)):
+        st[name][(Ellipsis,) + inner] = arr
+
+    big = problem(N, 48, 36)
+    o = (N - n) // 2
+    win = (slice(o, o + n),) * 3
+    big.c[win], big.rho[win], big.beta[win], big.label[win] = wc, wr, wb, wl
+    _say("skull_3d-like 1024^3, 96^3 window, random 16^3 block, %d steps (graph chunk 2)" % steps)
+    dom = fw2.from_problem(big, device="cuda:0", cap_steps=steps)
+    dom.set_graph_chunk(2)
+    buf = torch.zeros(dom.field_numel(), dtype=torch.float32, device="cuda:0")
+    views = dom.field_views(buf)
+    for name, arr in st.items():
+        views[name][(Ellipsis,) + win] = torch.from_numpy(arr).to("cuda:0")
+    dom.write_fields_device(buf)
+    del buf, views
+    dom.step(steps)
+    torch.cuda.synchronize()
+    out = dom.read_fields_device()
+    views = dom.field_views(out)
+    f = {name: views[name][(Ellipsis,) + win].cpu().numpy() for name in st}
+    for name in st:                      # every sample outside the window is still exactly zero
+        views[name][(Ellipsis,) + win] = 0.0
+    outside = float(out.abs().max().item())
+    del out, views
+    dom.destroy_domain()
+    torch.cuda.empty_cache()
+    assert outside == 0.0, outside
+    ref, _ = oracle_run(small, steps, state=st)
+    # in the oracle nothing reached the window's 6-cell layers (an 8-cell margin is zero)
+    for name in st:
+        a = np.abs(getattr(ref, name))
+        for ax in range(3):
+            lo = [slice(None)] * a.ndim
+            hi = [slice(None)] * a.ndim
+            lo[a.ndim - 3 + ax] = slice(0, 8)
+            hi[a.ndim - 3 + ax] = slice(n - 8, n)
+            assert a[tuple(lo)].max() == 0.0 and a[tuple(hi)].max() == 0.0, (name, ax)
+    compare(f, None, ref, None, "skull_3d_1024_window", prob=small)
+
+
 # ---------------------------------------------------------- edge cases ---
 
 def test_degenerate_grids():
