@@ -39,7 +39,7 @@ typedef enum {
     FW2_E_UNSUPPORTED = 6   /* valid request this build does not implement */
 } fw2_status;
 
-#define FW2_MAX_RELAX 8     /* largest number of relaxation mechanisms L (batched stepping: 4) */
+#define FW2_MAX_RELAX 8     /* largest number of relaxation mechanisms L */
 #define FW2_MAX_LABELS 256  /* relaxation tuples addressable by a uint8 label */
 
 /* Field selection for fw2_read_fields / fw2_write_fields.  Selected fields
@@ -76,8 +76,8 @@ enum { FW2_RELAX_PRINTED = 0, FW2_RELAX_CENTRED = 1 };
  *     r^2 of the two cells it lies between.  The weights are fixed cubic
  *     polynomials in r^2 (the Taylor conditions are linear in the weights
  *     with right-hand side 1, r^2, r^4, r^6), evaluated in the kernels from
- *     rho and kappa0; fd_r is then unused.  Not available to the batched
- *     path or the adjoint (FW2_E_UNSUPPORTED there). */
+ *     rho and kappa0; fd_r is then unused.  Not available to the adjoint
+ *     (FW2_E_UNSUPPORTED there). */
 enum { FW2_STENCIL_GLOBAL = 0, FW2_STENCIL_LOCAL = 1 };
 
 typedef struct {
@@ -211,9 +211,11 @@ fw2_status fw2_adjoint_step(fw2_domain *dom, const void *dev_state, const void *
 fw2_status fw2_adjoint_gradient(fw2_domain *dom, float *dst, int32_t dst_kind);
 
 /* ---- Batched stepping of many 2D domains (continuous batching) ----------
- * A batch advances several resident 2D domains of any sizes, L and memory
- * scheme with one launch per phase: blocks of a fixed grid walk the tiles of
- * every active domain (the per-tile arithmetic is the single-domain sweep's,
+ * A batch advances several resident 2D domains of any sizes, L, memory
+ * scheme and stencil mode with one launch per phase (two when domains with
+ * more than four mechanisms are present: those run in a launch of their own,
+ * in 256-column tiles): blocks of a fixed grid walk the tiles of every active
+ * domain (the per-tile arithmetic is the single-domain sweep's,
  * so results are bitwise those of stepping each domain alone).  Each domain
  * stops by itself when its step counter reaches its own n_steps, so domains
  * with different step counts share step loops; the loop is captured as a HIP
@@ -229,8 +231,9 @@ fw2_status fw2_adjoint_gradient(fw2_domain *dom, float *dst, int32_t dst_kind);
  *     batch stream (the domains' own streams are not used meanwhile).
  *   fw2_batch_set_tile: tile of the batched sweep, cols = 64 or 256 columns by
  *     rows >= 1 rows; only while the batch is empty.
- * Errors: FW2_E_INVALID for bad arguments, FW2_E_UNSUPPORTED for 3D domains,
- * FW2_E_HIP for runtime failures. */
+ * Errors: FW2_E_INVALID for bad arguments, FW2_E_UNSUPPORTED for 3D domains
+ * and for domains with more than four mechanisms when the tile has 64
+ * columns, FW2_E_HIP for runtime failures. */
 typedef struct fw2_batch fw2_batch;
 fw2_status fw2_batch_workspace_bytes(int32_t max_domains, uint64_t *bytes);
 fw2_status fw2_batch_create(int32_t max_domains, void *dev_workspace, uint64_t workspace_bytes,

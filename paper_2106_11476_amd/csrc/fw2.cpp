@@ -794,6 +794,7 @@ struct fw2_batch {
     int grid_blocks = 2048;
     int rows = 4;
     int bx = 256;
+    unsigned classes = 0;               // launch classes present in the table (fw2::batch_class)
 };
 
 namespace {
@@ -812,7 +813,7 @@ fw2_status batch_build_graph(fw2_batch *b)
     FW2_HIP(hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
     for (int k = 0; k < b->graph_chunk && e == hipSuccess; ++k)
-        e = fw2::launch_batch_step(b->dev, b->max_domains, b->grid_blocks, b->bx, b->capture);
+        e = fw2::launch_batch_step(b->dev, b->max_domains, b->grid_blocks, b->bx, b->classes, b->capture);
     hipGraph_t graph = nullptr;
     hipError_t e2 = hipStreamEndCapture(b->capture, &graph);
     if (e != hipSuccess || e2 != hipSuccess) {
@@ -887,9 +888,8 @@ fw2_status fw2_batch_set_domains(fw2_batch *b, int32_t n, fw2_domain *const *dom
         const fw2_domain *d = domains[k];
         if (!d) return fail(FW2_E_INVALID, "NULL domain");
         if (d->desc.ndim != 2) return fail(FW2_E_UNSUPPORTED, "batched stepping is 2D only");
-        if (d->desc.stencil_mode != FW2_STENCIL_GLOBAL)
-            return fail(FW2_E_UNSUPPORTED, "batched stepping uses global stencil weights only");
-        if (d->desc.n_relax > 4) return fail(FW2_E_UNSUPPORTED, "batched stepping takes at most 4 mechanisms");
+        if (d->desc.n_relax > 4 && b->bx != 256)
+            return fail(FW2_E_UNSUPPORTED, "batched domains with more than 4 mechanisms need 256-column tiles");
         if (d->step >= n_steps[k]) return fail(FW2_E_INVALID, "domain already at or past its n_steps");
         for (int32_t q = 0; q < k; ++q)
             if (domains[q] == d) return fail(FW2_E_INVALID, "domain listed twice");
@@ -901,8 +901,10 @@ fw2_status fw2_batch_set_domains(fw2_batch *b, int32_t n, fw2_domain *const *dom
     std::memset(&T, 0, sizeof(T));
     T.rows = b->rows;
     int tiles = 0, srcs = 0;
+    unsigned classes = 0;
     for (int32_t k = 0; k < n; ++k) {
         fw2_domain *d = domains[k];
+        classes |= 1u << fw2::batch_class(d->desc.n_relax, d->args.local_stencil);
         // the domain's own queued work must be finished before the batch stream touches it
         FW2_HIP(hipStreamSynchronize(d->stream));
         fw2::BatchEntry &e = T.e[k];
@@ -925,6 +927,8 @@ fw2_status fw2_batch_set_domains(fw2_batch *b, int32_t n, fw2_domain *const *dom
     T.n = n;
     T.total_tiles = tiles;
     T.total_src = srcs;
+    if (classes != b->classes) batch_drop_graph(b);    // the captured launches differ
+    b->classes = classes;
     FW2_HIP(hipMemcpyAsync(b->dev, &T, sizeof(T), hipMemcpyHostToDevice, b->stream));
     FW2_HIP(hipStreamSynchronize(b->stream));
     return FW2_OK;
@@ -943,7 +947,7 @@ fw2_status fw2_batch_step(fw2_batch *b, int32_t n)
         }
         for (; left >= b->graph_chunk; left -= b->graph_chunk) FW2_HIP(hipGraphLaunch(b->graph, b->stream));
     }
-    for (; left > 0; --left) FW2_HIP(fw2::launch_batch_step(b->dev, b->max_domains, b->grid_blocks, b->bx, b->stream));
+    for (; left > 0; --left) FW2_HIP(fw2::launch_batch_step(b->dev, b->max_domains, b->grid_blocks, b->bx, b->classes, b->stream));
     for (size_t k = 0; k < b->doms.size(); ++k)
         b->doms[k]->step = std::min<int64_t>(b->doms[k]->step + n, b->target[k]);
     return FW2_OK;

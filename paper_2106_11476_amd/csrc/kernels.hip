@@ -1000,9 +1000,42 @@ __device__ __forceinline__ int batch_entry_of_tile(const BatchTable *__restrict_
     return d;
 }
 
-template <bool PRESSURE, int BX>
+// One tile of one batch entry with the single-domain sweep's per-tile code.
+template <bool PRESSURE, int BX, int L, bool C, bool PP>
+__device__ __forceinline__ void batch_tile(const StepArgs &sa, int rows, int x0, int y0, float (*r0)[BX + 8],
+                                           float (*r1)[BX + 2], float (*r2)[BX + 1])
+{
+    if (PRESSURE)
+        pressure_tile2d<L, C, BX, false, PP>(sa, rows, x0, y0, r0, r1);
+    else
+        velocity_tile2d<L, C, BX, false, PP>(sa, rows, x0, y0, r0, r2, reinterpret_cast<float(*)[BX + 1]>(&r1[0][0]));
+}
+
+// Mechanism counts L0 .. L0 + 3 and both memory-variable schemes:
+// key = (L - L0) * 2 + scheme.
+template <bool PRESSURE, int BX, int L0, bool PP>
+__device__ __forceinline__ void batch_dispatch(int key, const StepArgs &sa, int rows, int x0, int y0,
+                                               float (*r0)[BX + 8], float (*r1)[BX + 2], float (*r2)[BX + 1])
+{
+    switch (key) {
+#define FW2_BCASE(K, DL, C) \
+    case K: batch_tile<PRESSURE, BX, L0 + DL, C, PP>(sa, rows, x0, y0, r0, r1, r2); break;
+    FW2_BCASE(0, 0, false) FW2_BCASE(1, 0, true) FW2_BCASE(2, 1, false) FW2_BCASE(3, 1, true)
+    FW2_BCASE(4, 2, false) FW2_BCASE(5, 2, true) FW2_BCASE(6, 3, false) FW2_BCASE(7, 3, true)
+#undef FW2_BCASE
+    default: break;
+    }
+}
+
+// One phase of the entries of one class of the table: CLASS bit 0 set for
+// 5..8 mechanisms (else 1..4), bit 1 set for per-point stencil weights.
+// Each class present gets a launch of its own, so that the larger register
+// demand of many mechanisms or per-point weights does not lower the
+// occupancy of the common class; entries of other classes are skipped.
+template <bool PRESSURE, int BX, int CLASS>
 __global__ void __launch_bounds__(BX) batch_phase(const BatchTable *__restrict__ T)
 {
+    constexpr bool MANY = (CLASS & 1) != 0, PP = (CLASS & 2) != 0;
     __shared__ float r0[4][BX + 8];
     __shared__ float r1[3][BX + 2];
     __shared__ float r2[3][BX + 1];
@@ -1011,6 +1044,7 @@ __global__ void __launch_bounds__(BX) batch_phase(const BatchTable *__restrict__
     for (int t = blockIdx.x; t < total; t += gridDim.x) {
         const int d = batch_entry_of_tile(T, t);
         const BatchEntry &e = T->e[d];
+        if (batch_class(e.L, e.a.local_stencil) != CLASS) continue;     // uniform over the block
         const long long step = *e.rcv.step;
         // pressure phase of step s runs while the counter reads s; velocity after it moved to s + 1
         const bool active = PRESSURE ? step < e.n_steps : (step >= 1 && step <= e.n_steps);
@@ -1024,37 +1058,8 @@ __global__ void __launch_bounds__(BX) batch_phase(const BatchTable *__restrict__
         const int nbx = (sa.geo.n[0] + BX - 1) / BX;
         const int lt = t - e.tile_base;
         const int x0 = (lt % nbx) * BX, y0 = (lt / nbx) * rows;
-        const int key = e.L * 2 + e.scheme;
-        if (PRESSURE) {
-            float(*sx)[BX + 8] = r0;
-            float(*sy)[BX + 2] = r1;
-            switch (key) {
-            case 2: pressure_tile2d<1, false, BX, false, false>(sa, rows, x0, y0, sx, sy); break;
-            case 3: pressure_tile2d<1, true, BX, false, false>(sa, rows, x0, y0, sx, sy); break;
-            case 4: pressure_tile2d<2, false, BX, false, false>(sa, rows, x0, y0, sx, sy); break;
-            case 5: pressure_tile2d<2, true, BX, false, false>(sa, rows, x0, y0, sx, sy); break;
-            case 6: pressure_tile2d<3, false, BX, false, false>(sa, rows, x0, y0, sx, sy); break;
-            case 7: pressure_tile2d<3, true, BX, false, false>(sa, rows, x0, y0, sx, sy); break;
-            case 8: pressure_tile2d<4, false, BX, false, false>(sa, rows, x0, y0, sx, sy); break;
-            case 9: pressure_tile2d<4, true, BX, false, false>(sa, rows, x0, y0, sx, sy); break;
-            default: break;
-            }
-        } else {
-            float(*sp)[BX + 8] = r0;
-            float(*sr)[BX + 1] = r2;
-            float(*sk)[BX + 1] = reinterpret_cast<float(*)[BX + 1]>(&r1[0][0]);
-            switch (key) {
-            case 2: velocity_tile2d<1, false, BX, false, false>(sa, rows, x0, y0, sp, sr, sk); break;
-            case 3: velocity_tile2d<1, true, BX, false, false>(sa, rows, x0, y0, sp, sr, sk); break;
-            case 4: velocity_tile2d<2, false, BX, false, false>(sa, rows, x0, y0, sp, sr, sk); break;
-            case 5: velocity_tile2d<2, true, BX, false, false>(sa, rows, x0, y0, sp, sr, sk); break;
-            case 6: velocity_tile2d<3, false, BX, false, false>(sa, rows, x0, y0, sp, sr, sk); break;
-            case 7: velocity_tile2d<3, true, BX, false, false>(sa, rows, x0, y0, sp, sr, sk); break;
-            case 8: velocity_tile2d<4, false, BX, false, false>(sa, rows, x0, y0, sp, sr, sk); break;
-            case 9: velocity_tile2d<4, true, BX, false, false>(sa, rows, x0, y0, sp, sr, sk); break;
-            default: break;
-            }
-        }
+        const int key = (e.L - (MANY ? 5 : 1)) * 2 + e.scheme;
+        batch_dispatch<PRESSURE, BX, MANY ? 5 : 1, PP>(key, sa, rows, x0, y0, r0, r1, r2);
         __syncthreads();                            // LDS rings and sa are reused by the next tile
     }
 }
@@ -1177,20 +1182,27 @@ hipError_t launch_receivers(const SparseArgs &s, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_batch_step(const BatchTable *T, int n_entries_max, int grid_blocks, int bx, hipStream_t st)
+template <bool PRESSURE>
+void launch_batch_phase(const BatchTable *T, int grid_blocks, int bx, unsigned classes, hipStream_t st)
 {
-    if (bx == 64) {
-        hipLaunchKernelGGL((batch_phase<true, 64>), dim3(grid_blocks * 4), dim3(64), 0, st, T);
-    } else {
-        hipLaunchKernelGGL((batch_phase<true, 256>), dim3(grid_blocks), dim3(256), 0, st, T);
+    if (bx == 64) {                                 // classes 0 and 2 (at most 4 mechanisms)
+        if (classes & 1u) hipLaunchKernelGGL((batch_phase<PRESSURE, 64, 0>), dim3(grid_blocks * 4), dim3(64), 0, st, T);
+        if (classes & 4u) hipLaunchKernelGGL((batch_phase<PRESSURE, 64, 2>), dim3(grid_blocks * 4), dim3(64), 0, st, T);
+        return;
     }
+    if (classes & 1u) hipLaunchKernelGGL((batch_phase<PRESSURE, 256, 0>), dim3(grid_blocks), dim3(256), 0, st, T);
+    if (classes & 2u) hipLaunchKernelGGL((batch_phase<PRESSURE, 256, 1>), dim3(grid_blocks), dim3(256), 0, st, T);
+    if (classes & 4u) hipLaunchKernelGGL((batch_phase<PRESSURE, 256, 2>), dim3(grid_blocks), dim3(256), 0, st, T);
+    if (classes & 8u) hipLaunchKernelGGL((batch_phase<PRESSURE, 256, 3>), dim3(grid_blocks), dim3(256), 0, st, T);
+}
+
+hipError_t launch_batch_step(const BatchTable *T, int n_entries_max, int grid_blocks, int bx, unsigned classes,
+                             hipStream_t st)
+{
+    launch_batch_phase<true>(T, grid_blocks, bx, classes, st);
     hipLaunchKernelGGL(batch_sources, dim3(256), dim3(256), 0, st, T);
     hipLaunchKernelGGL(batch_receivers, dim3(n_entries_max), dim3(256), 0, st, T);
-    if (bx == 64) {
-        hipLaunchKernelGGL((batch_phase<false, 64>), dim3(grid_blocks * 4), dim3(64), 0, st, T);
-    } else {
-        hipLaunchKernelGGL((batch_phase<false, 256>), dim3(grid_blocks), dim3(256), 0, st, T);
-    }
+    launch_batch_phase<false>(T, grid_blocks, bx, classes, st);
     return hipGetLastError();
 }
 

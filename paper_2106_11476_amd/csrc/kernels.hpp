@@ -109,8 +109,17 @@ struct BatchTable {
     BatchEntry e[kMaxBatch];
 };
 
+// Launch class of a batch entry: bit 0 for 5..8 mechanisms, bit 1 for
+// per-point stencil weights.
+__host__ __device__ inline int batch_class(int L, int local_stencil)
+{
+    return (L > 4 ? 1 : 0) | (local_stencil ? 2 : 0);
+}
+
+// One step of every entry.  classes: bit c set when the table holds entries
+// of class c (classes 1 and 3 need bx = 256).
 hipError_t launch_batch_step(const BatchTable *dev_table, int n_entries_max, int grid_blocks, int bx,
-                             hipStream_t stream);
+                             unsigned classes, hipStream_t stream);
 
 // Discrete adjoint of one step (adjoint.hip): device arrays of the adjoint
 // state (same layout as the forward state block) and the per-step temporaries.

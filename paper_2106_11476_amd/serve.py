@@ -111,6 +111,7 @@ class Server:
         self.stream = torch.cuda.Stream(device=self.device)
         self.setup_stream = torch.cuda.Stream(device=self.device)
         self.batch = fw2.Batch(max_domains=self.max_active, device=self.device, stream=self.stream)
+        self.tile = tuple(tile)
         self.batch.set_tile(*tile)
 
     def _start(self, r):
@@ -123,6 +124,8 @@ class Server:
     def run(self, requests, clock=time.perf_counter):
         """Serve the requests (sorted by arrival); returns Stats."""
         queue = sorted(requests, key=lambda r: (r.arrival, r.rid))
+        if self.tile[0] != 256 and any(int(r.problem.n_relax) > 4 for r in queue):
+            raise ValueError("requests with more than four mechanisms need 256-column tiles")
         for r in queue:
             r.footprint = footprint_bytes(r.problem, r.n_steps)
             if r.footprint > self.budget:
@@ -246,8 +249,14 @@ def autotune_tile(problems, candidates=((256, 2), (256, 4), (256, 8), (64, 4), (
                   steps=32, device="cuda:0"):
     """Pick the batched sweep's tile (columns, rows) by timing each candidate
     on a batch of zero-state copies of the given problems (sources are not
-    attached, so the fields stay zero and nothing is consumed)."""
+    attached, so the fields stay zero and nothing is consumed).  Domains with
+    more than four mechanisms run in 256-column tiles only, so with such a
+    problem in the mix the 64-column candidates are left out."""
     import torch
+    if any(int(p.n_relax) > 4 for p in problems):
+        candidates = tuple(c for c in candidates if c[0] == 256)
+    if not candidates:
+        raise ValueError("no candidate tile fits the problems")
     dev = torch.device(device)
     stream = torch.cuda.Stream(device=dev)
     doms = [fw2.Domain(p, device=dev, stream=stream) for p in problems]

@@ -102,7 +102,9 @@ def test_continuous_batching_results_are_mix_independent():
     mix = _mix()
     _say("continuous batching", len(mix))
     solo = [_solo(p, n)[1] for p, n in mix]
-    reqs = [serve.Request(rid=i, problem=p, n_steps=n, arrival=0.02 * i) for i, (p, n) in enumerate(mix)]
+    # arrivals 3 ms apart: each request alone takes 15-20 ms, so later ones
+    # arrive while earlier ones are on the device
+    reqs = [serve.Request(rid=i, problem=p, n_steps=n, arrival=0.003 * i) for i, (p, n) in enumerate(mix)]
     budget = int(2.2 * max(serve.footprint_bytes(p, n) for p, n in mix))
     srv = serve.Server(budget_bytes=budget, max_active=4, chunk=48)
     st = srv.run(reqs)
@@ -125,15 +127,95 @@ def test_autotuner_picks_a_candidate():
     assert best in cands and all(v > 0 for v in t.values())
 
 
-def test_batch_refuses_more_than_four_mechanisms():
+def _variant_mix():
+    """Domains of every launch class: global and per-point stencil weights,
+    1..4 and 5..8 mechanisms, both memory schemes, uneven sizes and steps."""
+    out = []
+    for k, (shape, L, mode, scheme, n) in enumerate([((200, 136), 3, 1, 1, 260), ((264, 96), 2, 0, 1, 300),
+                                                     ((150, 170), 6, 0, 1, 240), ((97, 131), 8, 1, 0, 200),
+                                                     ((320, 64), 4, 1, 0, 280)]):
+        p = W.random_medium(shape, L, 2, seed=40 + k, nb=8, ntr=6)
+        p.stencil_mode, p.relax_scheme = mode, scheme
+        rng = np.random.default_rng(k)
+        p.src_idx = np.unique(rng.integers(0, p.npts, 5)).astype(np.int64)
+        p.src_sig = np.zeros(p.src_idx.size, np.int32)
+        p.src_w = np.ones(p.src_idx.size, np.float32)
+        p.signals = W.gaussian_pulse(120, p.dt, 3e6, 3, 1e5)[None]
+        p.rcv_idx = rng.integers(0, p.npts, 7).astype(np.int64)
+        p.name = "variant_%d_L%d_mode%d" % (k, L, mode)
+        out.append((p, n))
+    return out
+
+
+@pytest.mark.parametrize("tile", [(256, 4), (256, 8), (64, 4)])
+def test_batch_of_every_launch_class_equals_solo_runs_bitwise(tile):
+    """Per-point stencil weights and 5..8 mechanisms in the batch (launches of
+    their own), mixed with the common class: every domain ends bitwise where
+    it ends alone.  64-column tiles take the domains with at most four
+    mechanisms and refuse the others."""
     torch = _torch()
     from paper_2106_11476_amd import fw2
-    prob = W.random_medium((40, 36), 5, 2, seed=3, nb=4, ntr=2)
-    _say("batch refuses L = 5")
-    dom = fw2.Domain(prob, device="cuda:0")
-    batch = fw2.Batch(max_domains=2, device="cuda:0")
-    with pytest.raises(fw2.Fw2Error, match="UNSUPPORTED"):
-        batch.set_domains([dom], [10])
-    torch.cuda.synchronize()
-    batch.destroy()
-    dom.destroy_domain()
+    mix = _variant_mix()
+    if tile[0] == 64:
+        many = [(p, n) for p, n in mix if p.n_relax > 4]
+        mix = [(p, n) for p, n in mix if p.n_relax <= 4]
+    _say("batch of every class, tile", tile, [(p.shape, p.n_relax, p.stencil_mode, n) for p, n in mix])
+    solo = [_solo(p, n) for p, n in mix]
+    stream = torch.cuda.Stream()
+    doms = [fw2.from_problem(p, device="cuda:0", stream=stream, cap_steps=n) for p, n in mix]
+    b = fw2.Batch(max_domains=8, stream=stream)
+    b.set_tile(*tile)
+    if tile[0] == 64:
+        big = fw2.from_problem(many[0][0], device="cuda:0", stream=stream, cap_steps=many[0][1])
+        with pytest.raises(fw2.Fw2Error, match="UNSUPPORTED"):
+            b.set_domains(doms + [big], [n for _, n in mix] + [many[0][1]])
+        big.destroy_domain()
+    b.set_domains(doms, [n for _, n in mix])
+    left = max(n for _, n in mix)
+    while left > 0:
+        k = min(left, 71)
+        b.step(k)
+        left -= k
+    stream.synchronize()
+    for (p, n), d, (f, tr) in zip(mix, doms, solo):
+        assert d.current_step() == n
+        g = d.read_fields(fw2.FIELD_ALL)
+        for key in f:
+            assert np.array_equal(f[key], g[key]), (p.name, key)
+        assert np.array_equal(tr, d.trace.cpu().numpy()), p.name
+    b.set_domains([], [])
+    b.destroy()
+    for d in doms:
+        d.destroy_domain()
+
+
+def test_batched_per_point_weights_match_oracle():
+    torch = _torch()
+    from paper_2106_11476_amd import fw2
+    p, _ = _variant_mix()[0]
+    n = 200
+    _say("batch with per-point weights vs oracle", p.shape, p.n_relax)
+    stream = torch.cuda.Stream()
+    d = fw2.from_problem(p, device="cuda:0", stream=stream, cap_steps=n)
+    b = fw2.Batch(max_domains=2, stream=stream)
+    b.set_domains([d], [n])
+    b.step(n)
+    stream.synchronize()
+    f = d.read_fields(fw2.FIELD_P)
+    ref, rtr = solver.run(p, n)
+    peak = max(np.abs(ref.p).max(), np.abs(rtr).max())
+    assert np.linalg.norm(f["p"] - ref.p) / np.linalg.norm(ref.p) < 1e-4
+    assert np.abs(f["p"] - ref.p).max() / peak < 1e-3
+    tr = d.trace.cpu().numpy()
+    assert np.linalg.norm(tr - rtr) / np.linalg.norm(rtr) < 1e-4
+    b.set_domains([], [])
+    b.destroy()
+    d.destroy_domain()
+
+
+def test_autotuner_keeps_256_columns_for_many_mechanisms():
+    _torch()
+    from paper_2106_11476_amd import serve
+    probs = [p for p, _ in _variant_mix()[1:3]]
+    best, t = serve.autotune_tile(probs, candidates=((256, 4), (64, 8)), steps=8)
+    assert best == (256, 4) and set(t) == {(256, 4)}
