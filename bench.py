@@ -151,15 +151,16 @@ def probe_copy(torch, dev, mib, reps=10):
 
 
 def serving_leg(seed=4):
-    """Continuous batching vs the plain one-at-a-time solver on two seeded
-    request streams: the heterogeneous 2D recipe at 512^2-1024^2 (the served
-    workload's recipe, scaled so the leg takes seconds) and small 128^2-384^2
-    grids.  Capacity: all requests queued at t = 0.  Latency: Poisson
-    arrivals at 1.2x the plain solver's capacity."""
+    """Continuous batching vs the plain one-at-a-time solver on three seeded
+    request streams of the heterogeneous 2D recipe: 8 requests at the served
+    workload's own sizes and step counts (1024^2-3072^2), 48 at 512^2-1024^2
+    and 96 small 128^2-384^2 grids.  Capacity: all requests queued at t = 0.
+    Latency: Poisson arrivals at 1.2x the plain solver's capacity."""
     import workloads as W
     from paper_2106_11476_amd import serve
     out = {}
-    for name, (n, sides, step) in (("heterogeneous_512_1024", (48, (512, 1024), 128)),
+    for name, (n, sides, step) in (("workload_1024_3072", (8, (1024, 3072), 256)),
+                                   ("heterogeneous_512_1024", (48, (512, 1024), 128)),
                                    ("small_128_384", (96, (128, 384), 64))):
         raw = W.serving_requests(n=n, seed=seed, sides=sides, side_step=step)
         upd = sum(p.npts * k for p, k, _ in raw)

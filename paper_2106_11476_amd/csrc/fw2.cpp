@@ -791,7 +791,6 @@ struct fw2_batch {
     hipStream_t capture = nullptr;
     hipGraphExec_t graph = nullptr;
     int graph_chunk = 32;
-    int grid_blocks = 2048;
     int rows = 4;
     int bx = 256;
     unsigned classes = 0;               // launch classes present in the table (fw2::batch_class)
@@ -813,7 +812,7 @@ fw2_status batch_build_graph(fw2_batch *b)
     FW2_HIP(hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
     for (int k = 0; k < b->graph_chunk && e == hipSuccess; ++k)
-        e = fw2::launch_batch_step(b->dev, b->max_domains, b->grid_blocks, b->bx, b->classes, b->capture);
+        e = fw2::launch_batch_step(b->dev, b->max_domains, b->bx, b->classes, b->capture);
     hipGraph_t graph = nullptr;
     hipError_t e2 = hipStreamEndCapture(b->capture, &graph);
     if (e != hipSuccess || e2 != hipSuccess) {
@@ -865,6 +864,7 @@ fw2_status fw2_batch_create(int32_t max_domains, void *dev_workspace, uint64_t w
     if (workspace_bytes < need) return fail(FW2_E_NOMEM, "batch workspace too small");
     fw2_batch *b = new (std::nothrow) fw2_batch();
     if (!b) return fail(FW2_E_NOMEM, "host allocation failed");
+    fw2::prepare_batch_launches();
     b->max_domains = max_domains;
     b->dev = (fw2::BatchTable *)dev_workspace;
     b->stream = (hipStream_t)stream;
@@ -947,7 +947,7 @@ fw2_status fw2_batch_step(fw2_batch *b, int32_t n)
         }
         for (; left >= b->graph_chunk; left -= b->graph_chunk) FW2_HIP(hipGraphLaunch(b->graph, b->stream));
     }
-    for (; left > 0; --left) FW2_HIP(fw2::launch_batch_step(b->dev, b->max_domains, b->grid_blocks, b->bx, b->classes, b->stream));
+    for (; left > 0; --left) FW2_HIP(fw2::launch_batch_step(b->dev, b->max_domains, b->bx, b->classes, b->stream));
     for (size_t k = 0; k < b->doms.size(); ++k)
         b->doms[k]->step = std::min<int64_t>(b->doms[k]->step + n, b->target[k]);
     return FW2_OK;

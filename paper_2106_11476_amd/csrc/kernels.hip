@@ -1039,9 +1039,20 @@ __global__ void __launch_bounds__(BX) batch_phase(const BatchTable *__restrict__
     __shared__ float r0[4][BX + 8];
     __shared__ float r1[3][BX + 2];
     __shared__ float r2[3][BX + 1];
-    __shared__ StepArgs sa;
     const int total = T->total_tiles, rows = T->rows;
-    for (int t = blockIdx.x; t < total; t += gridDim.x) {
+    // Blocks are dealt to the 8 XCDs round-robin; with a grid that is a
+    // multiple of 8, the blocks of XCD x walk one contiguous eighth of the
+    // tile list, so neighbouring tiles (which share halo rows) meet in the
+    // same L2.
+    int t = blockIdx.x, t_end = total, t_step = gridDim.x;
+    if (gridDim.x % 8 == 0) {
+        const int x = blockIdx.x % 8, q = total / 8, rem = total % 8;
+        const int start = x * q + min(x, rem);
+        t = start + blockIdx.x / 8;
+        t_end = start + q + (x < rem ? 1 : 0);
+        t_step = gridDim.x / 8;
+    }
+    for (; t < t_end; t += t_step) {
         const int d = batch_entry_of_tile(T, t);
         const BatchEntry &e = T->e[d];
         if (batch_class(e.L, e.a.local_stencil) != CLASS) continue;     // uniform over the block
@@ -1049,18 +1060,16 @@ __global__ void __launch_bounds__(BX) batch_phase(const BatchTable *__restrict__
         // pressure phase of step s runs while the counter reads s; velocity after it moved to s + 1
         const bool active = PRESSURE ? step < e.n_steps : (step >= 1 && step <= e.n_steps);
         if (!active) continue;                      // uniform over the block
-        {
-            const int *src = reinterpret_cast<const int *>(&e.a);
-            int *dst = reinterpret_cast<int *>(&sa);
-            for (int w = threadIdx.x; w < (int)(sizeof(StepArgs) / 4); w += BX) dst[w] = src[w];
-        }
-        __syncthreads();
+        // the entry's arguments are read in place: the address is uniform
+        // over the block, so they load into scalar registers as a kernel's
+        // own arguments do
+        const StepArgs &sa = e.a;
         const int nbx = (sa.geo.n[0] + BX - 1) / BX;
         const int lt = t - e.tile_base;
         const int x0 = (lt % nbx) * BX, y0 = (lt / nbx) * rows;
         const int key = (e.L - (MANY ? 5 : 1)) * 2 + e.scheme;
         batch_dispatch<PRESSURE, BX, MANY ? 5 : 1, PP>(key, sa, rows, x0, y0, r0, r1, r2);
-        __syncthreads();                            // LDS rings and sa are reused by the next tile
+        __syncthreads();                            // the LDS rings are reused by the next tile
     }
 }
 
@@ -1182,28 +1191,69 @@ hipError_t launch_receivers(const SparseArgs &s, hipStream_t st)
     return hipGetLastError();
 }
 
-template <bool PRESSURE>
-void launch_batch_phase(const BatchTable *T, int grid_blocks, int bx, unsigned classes, hipStream_t st)
+// Persistent grid of a batch kernel: as many blocks as fit on the device at
+// once (occupancy query), rounded down to a multiple of 8 XCDs, so that no
+// block waits for a free slot while others hold tiles.
+template <bool PRESSURE, int BX, int CLASS>
+int batch_grid()
 {
-    if (bx == 64) {                                 // classes 0 and 2 (at most 4 mechanisms)
-        if (classes & 1u) hipLaunchKernelGGL((batch_phase<PRESSURE, 64, 0>), dim3(grid_blocks * 4), dim3(64), 0, st, T);
-        if (classes & 4u) hipLaunchKernelGGL((batch_phase<PRESSURE, 64, 2>), dim3(grid_blocks * 4), dim3(64), 0, st, T);
-        return;
-    }
-    if (classes & 1u) hipLaunchKernelGGL((batch_phase<PRESSURE, 256, 0>), dim3(grid_blocks), dim3(256), 0, st, T);
-    if (classes & 2u) hipLaunchKernelGGL((batch_phase<PRESSURE, 256, 1>), dim3(grid_blocks), dim3(256), 0, st, T);
-    if (classes & 4u) hipLaunchKernelGGL((batch_phase<PRESSURE, 256, 2>), dim3(grid_blocks), dim3(256), 0, st, T);
-    if (classes & 8u) hipLaunchKernelGGL((batch_phase<PRESSURE, 256, 3>), dim3(grid_blocks), dim3(256), 0, st, T);
+    static const int grid = [] {
+        int dev = 0, cus = 0, per_cu = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_phase<PRESSURE, BX, CLASS>, BX, 0) !=
+                hipSuccess ||
+            cus <= 0 || per_cu <= 0)
+            return 2048;
+        const int g = cus * per_cu;
+        return g >= 8 ? g - g % 8 : g;
+    }();
+    return grid;
 }
 
-hipError_t launch_batch_step(const BatchTable *T, int n_entries_max, int grid_blocks, int bx, unsigned classes,
-                             hipStream_t st)
+template <bool PRESSURE, int BX, int CLASS>
+void launch_batch_class(const BatchTable *T, hipStream_t st)
 {
-    launch_batch_phase<true>(T, grid_blocks, bx, classes, st);
+    hipLaunchKernelGGL((batch_phase<PRESSURE, BX, CLASS>), dim3(batch_grid<PRESSURE, BX, CLASS>()), dim3(BX), 0, st, T);
+}
+
+template <bool PRESSURE>
+void launch_batch_phase(const BatchTable *T, int bx, unsigned classes, hipStream_t st)
+{
+    if (bx == 64) {                                 // classes 0 and 2 (at most 4 mechanisms)
+        if (classes & 1u) launch_batch_class<PRESSURE, 64, 0>(T, st);
+        if (classes & 4u) launch_batch_class<PRESSURE, 64, 2>(T, st);
+        return;
+    }
+    if (classes & 1u) launch_batch_class<PRESSURE, 256, 0>(T, st);
+    if (classes & 2u) launch_batch_class<PRESSURE, 256, 1>(T, st);
+    if (classes & 4u) launch_batch_class<PRESSURE, 256, 2>(T, st);
+    if (classes & 8u) launch_batch_class<PRESSURE, 256, 3>(T, st);
+}
+
+hipError_t launch_batch_step(const BatchTable *T, int n_entries_max, int bx, unsigned classes, hipStream_t st)
+{
+    launch_batch_phase<true>(T, bx, classes, st);
     hipLaunchKernelGGL(batch_sources, dim3(256), dim3(256), 0, st, T);
     hipLaunchKernelGGL(batch_receivers, dim3(n_entries_max), dim3(256), 0, st, T);
-    launch_batch_phase<false>(T, grid_blocks, bx, classes, st);
+    launch_batch_phase<false>(T, bx, classes, st);
     return hipGetLastError();
+}
+
+void prepare_batch_launches()
+{
+    (void)batch_grid<true, 64, 0>();
+    (void)batch_grid<true, 64, 2>();
+    (void)batch_grid<false, 64, 0>();
+    (void)batch_grid<false, 64, 2>();
+    (void)batch_grid<true, 256, 0>();
+    (void)batch_grid<true, 256, 1>();
+    (void)batch_grid<true, 256, 2>();
+    (void)batch_grid<true, 256, 3>();
+    (void)batch_grid<false, 256, 0>();
+    (void)batch_grid<false, 256, 1>();
+    (void)batch_grid<false, 256, 2>();
+    (void)batch_grid<false, 256, 3>();
 }
 
 hipError_t launch_fill(float *dst, int64_t n, float value, hipStream_t st)

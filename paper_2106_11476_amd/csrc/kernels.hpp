@@ -118,8 +118,11 @@ __host__ __device__ inline int batch_class(int L, int local_stencil)
 
 // One step of every entry.  classes: bit c set when the table holds entries
 // of class c (classes 1 and 3 need bx = 256).
-hipError_t launch_batch_step(const BatchTable *dev_table, int n_entries_max, int grid_blocks, int bx,
-                             unsigned classes, hipStream_t stream);
+hipError_t launch_batch_step(const BatchTable *dev_table, int n_entries_max, int bx, unsigned classes,
+                             hipStream_t stream);
+// Sizes the persistent grids of the batch kernels (occupancy queries); call
+// outside stream capture before the first batched step.
+void prepare_batch_launches();
 
 // Discrete adjoint of one step (adjoint.hip): device arrays of the adjoint
 // state (same layout as the forward state block) and the per-step temporaries.
