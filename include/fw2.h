@@ -159,6 +159,13 @@ int64_t fw2_current_step(const fw2_domain *dom);
 /* Set the global step index (resume from a checkpoint).  Synchronises. */
 fw2_status fw2_set_current_step(fw2_domain *dom, int64_t step);
 
+/* Move the domain to another stream: finishes the work queued on its current
+ * stream, then queues every later call of this domain (steps, transfers,
+ * checkpoints, the adjoint) on stream (NULL: the default stream).  The caller
+ * keeps the stream alive while the domain uses it.  A domain can be built on
+ * a setup stream while other work runs, then stepped on a serving stream. */
+fw2_status fw2_set_stream(fw2_domain *dom, void *stream);
+
 /* Steps captured per HIP graph replay (0 disables graphs; default 32).
  * Graph and direct launches give bitwise identical results. */
 fw2_status fw2_set_graph_chunk(fw2_domain *dom, int32_t steps);

@@ -616,6 +616,15 @@ fw2_status fw2_set_current_step(fw2_domain *d, int64_t step)
     return FW2_OK;
 }
 
+fw2_status fw2_set_stream(fw2_domain *d, void *stream)
+{
+    if (!d) return fail(FW2_E_STATE, "domain is NULL");
+    FW2_HIP(hipStreamSynchronize(d->stream));
+    d->stream = (hipStream_t)stream;
+    d->desc.stream = stream;
+    return FW2_OK;
+}
+
 fw2_status fw2_set_graph_chunk(fw2_domain *d, int32_t steps)
 {
     if (!d) return fail(FW2_E_STATE, "domain is NULL");

@@ -22,7 +22,7 @@ STENCIL_GLOBAL, STENCIL_LOCAL = 0, 1
 
 EXPORTS = ["fw2_workspace_bytes", "fw2_create_domain", "fw2_add_source", "fw2_add_receivers",
            "fw2_step", "fw2_read_fields", "fw2_write_fields", "fw2_current_step",
-           "fw2_set_current_step", "fw2_set_graph_chunk", "fw2_enable_kernel_timing",
+           "fw2_set_current_step", "fw2_set_stream", "fw2_set_graph_chunk", "fw2_enable_kernel_timing",
            "fw2_get_kernel_timing", "fw2_check_finite", "fw2_last_error", "fw2_destroy_domain",
            "fw2_batch_workspace_bytes", "fw2_batch_create", "fw2_batch_set_domains",
            "fw2_batch_step", "fw2_batch_set_tile", "fw2_batch_destroy",
@@ -70,6 +70,7 @@ def lib():
             "fw2_write_fields": [vp, u32, vp, i32],
             "fw2_set_current_step": [vp, i64],
             "fw2_set_graph_chunk": [vp, i32],
+            "fw2_set_stream": [vp, vp],
             "fw2_enable_kernel_timing": [vp, i32],
             "fw2_get_kernel_timing": [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)],
             "fw2_check_finite": [vp, ctypes.c_float],
@@ -224,6 +225,12 @@ class Domain:
 
     def set_graph_chunk(self, steps):
         _check(lib().fw2_set_graph_chunk(self._h, int(steps)))
+
+    def set_stream(self, stream):
+        """Queue this domain's later calls on another torch stream (after the
+        work on its current stream has finished)."""
+        _check(lib().fw2_set_stream(self._h, ctypes.c_void_p(stream.cuda_stream)))
+        self.stream = stream
 
     def enable_kernel_timing(self, enable=True):
         _check(lib().fw2_enable_kernel_timing(self._h, 1 if enable else 0))

@@ -91,17 +91,28 @@ class Server:
     budget_bytes -- device memory the resident requests may hold together
     max_active   -- largest number of requests advanced by one launch (<= 64)
     chunk        -- steps between admission / completion points
+    solo_points  -- requests of at least this many points are stepped alone
 
     Host work overlaps device work: arrived requests are admitted (arrival
     order, memory budget and slots counted over running, built and admitted
     requests); their domains are built on a separate setup stream while a
-    chunk of steps runs on the batch stream, and join the batch at the next
-    chunk boundary, when finished requests also hand back their traces.  With
+    chunk of steps runs on the serving stream, and join at the next chunk
+    boundary, when finished requests also hand back their traces.  With
     requests waiting to be built, chunks are kept short so that they join
     early.
+
+    Requests too small to fill the GPU share the batched launch.  A request
+    that fills it alone gains nothing from sharing and loses the reuse of its
+    fields in the device's last-level cache between the two phases of a step
+    (a batched phase sweeps every domain before the next phase starts), so
+    such requests are stepped alone with the single-domain kernels, one at a
+    time in arrival order, on the same stream after the batched launch; the
+    others wait resident, with their setup and read-back still overlapping
+    the device work.
     """
 
-    def __init__(self, budget_bytes, max_active=32, chunk=64, device="cuda:0", tile=(256, 4)):
+    def __init__(self, budget_bytes, max_active=32, chunk=64, device="cuda:0", tile=(256, 4),
+                 solo_points=2_000_000):
         import torch
         self.torch = torch
         self.device = torch.device(device)
@@ -113,6 +124,7 @@ class Server:
         self.batch = fw2.Batch(max_domains=self.max_active, device=self.device, stream=self.stream)
         self.tile = tuple(tile)
         self.batch.set_tile(*tile)
+        self.solo_points = int(solo_points)
 
     def _start(self, r):
         dom = fw2.Domain(r.problem, device=self.device, stream=self.setup_stream)
@@ -124,16 +136,18 @@ class Server:
     def run(self, requests, clock=time.perf_counter):
         """Serve the requests (sorted by arrival); returns Stats."""
         queue = sorted(requests, key=lambda r: (r.arrival, r.rid))
-        if self.tile[0] != 256 and any(int(r.problem.n_relax) > 4 for r in queue):
+        if self.tile[0] != 256 and any(int(r.problem.n_relax) > 4 and r.problem.npts < self.solo_points
+                                       for r in queue):
             raise ValueError("requests with more than four mechanisms need 256-column tiles")
         for r in queue:
             r.footprint = footprint_bytes(r.problem, r.n_steps)
             if r.footprint > self.budget:
                 raise ValueError("request %d needs %d bytes, above the budget" % (r.rid, r.footprint))
         active = []               # (request, domain) in the batch
+        solo = []                 # (request, domain) stepped alone, in arrival order
         staged = []               # (request, domain) built, joining at the next boundary
         pending = []              # admitted requests (memory reserved) not built yet
-        in_flight = False         # a chunk is queued on the batch stream
+        in_flight = False         # a chunk is queued on the serving stream
         stats = Stats()
         t0 = clock()
 
@@ -143,10 +157,10 @@ class Server:
             staged.append((r, self._start(r)))
             stats.t_build += clock() - tb
 
-        while queue or active or staged or pending:
+        while queue or active or solo or staged or pending:
             # admit arrived requests (arrival order; memory and slots counted
             # over running, built and admitted-but-unbuilt requests)
-            held = [r for r, _ in active] + [r for r, _ in staged] + pending
+            held = [r for r, _ in active] + [r for r, _ in solo] + [r for r, _ in staged] + pending
             new = admit(queue, sum(r.footprint for r in held), self.budget, self.max_active - len(held),
                         clock() - t0)
             for r in new:
@@ -155,7 +169,7 @@ class Server:
                 pending.append(r)
             # build while the device is busy with the chunk in flight; with an
             # idle device build one, so that stepping can start
-            if pending and not (in_flight or active or staged):
+            if pending and not (in_flight or active or solo or staged):
                 build_one()
             while pending and in_flight and not self.stream.query():
                 build_one()
@@ -166,42 +180,54 @@ class Server:
                 self.stream.synchronize()
                 stats.t_wait += clock() - tw
                 in_flight = False
-                finished = [(r, d) for r, d in active if d.current_step() >= r.n_steps]
+                finished = [(r, d) for r, d in active + solo if d.current_step() >= r.n_steps]
                 if finished:
                     tf = clock()
+                    changed = any(d.current_step() >= r.n_steps for r, d in active)
                     active = [(r, d) for r, d in active if d.current_step() < r.n_steps]
-                    changed = True
+                    solo = [(r, d) for r, d in solo if d.current_step() < r.n_steps]
                     for r, d in finished:
                         r.trace = d.trace.cpu().numpy()
                         r.done = clock() - t0
                         stats.latencies.append(r.done - r.arrival)
                         stats.completed += 1
                     stats.t_finish += clock() - tf
-            if staged:
-                active += staged
-                staged = []
-                changed = True
-            if changed:
+            for r, d in staged:
+                if r.problem.npts >= self.solo_points:
+                    d.set_stream(self.stream)
+                    solo.append((r, d))
+                else:
+                    active.append((r, d))
+                    changed = True
+            staged = []
+            if changed or finished:
                 tt = clock()
-                # the batch table stops referring to finished domains before they go
-                self.batch.set_domains([d for _, d in active], [r.n_steps for r, _ in active])
+                if changed:
+                    # the batch table stops referring to finished domains before they go
+                    self.batch.set_domains([d for _, d in active], [r.n_steps for r, _ in active])
                 for _, d in finished:
                     d.destroy_domain()
                 stats.t_table += clock() - tt
-            if not active:
+            if not active and not solo:
                 if queue and not pending:
                     wait = queue[0].arrival - (clock() - t0)
                     if wait > 0:
                         time.sleep(min(wait, 0.05))
                 continue
-            stats.peak_bytes = max(stats.peak_bytes, sum(r.footprint for r, _ in active))
-            stats.peak_active = max(stats.peak_active, len(active))
-            # run until the next event: the first completion, or (when requests
-            # wait to join) the next chunk boundary
-            to_done = min(r.n_steps - d.current_step() for r, d in active)
-            waiting = pending or (queue and len(active) < self.max_active)
-            k = min(to_done, self.chunk) if waiting else to_done
-            self.batch.step(max(int(k), 1))
+            stats.peak_bytes = max(stats.peak_bytes, sum(r.footprint for r, _ in active + solo))
+            stats.peak_active = max(stats.peak_active, len(active) + len(solo))
+            # run until the next event: the first completion among the batched
+            # requests and the solo request in turn, or (when requests wait to
+            # join) the next chunk boundary
+            left = [r.n_steps - d.current_step() for r, d in active + solo[:1]]
+            to_done = min(left)
+            waiting = pending or (queue and len(active) + len(solo) < self.max_active)
+            k = max(int(min(to_done, self.chunk) if waiting else to_done), 1)
+            if active:
+                self.batch.step(k)
+            if solo:
+                r, d = solo[0]
+                d.step(min(k, r.n_steps - d.current_step()))
             stats.chunks += 1
             in_flight = True
         stats.makespan = clock() - t0

@@ -118,6 +118,31 @@ def test_continuous_batching_results_are_mix_independent():
     assert s["p99_latency_s"] >= s["p50_latency_s"] > 0
 
 
+def test_serving_steps_large_requests_alone_in_arrival_order():
+    """With a size threshold inside the mix, the larger requests are stepped
+    alone (single-domain kernels, one at a time in arrival order) while the
+    smaller ones share the batched launch; every trace is still bitwise the
+    solo trace, and the large requests finish in arrival order."""
+    torch = _torch()
+    from paper_2106_11476_amd import serve
+    mix = _mix()
+    sizes = sorted(p.npts for p, _ in mix)
+    cut = sizes[len(sizes) // 2]
+    _say("hybrid serving, solo from", cut, "points", [(p.npts, n) for p, n in mix])
+    solo = [_solo(p, n)[1] for p, n in mix]
+    reqs = [serve.Request(rid=i, problem=p, n_steps=n, arrival=0.002 * i) for i, (p, n) in enumerate(mix)]
+    budget = int(4 * max(serve.footprint_bytes(p, n) for p, n in mix))
+    srv = serve.Server(budget_bytes=budget, max_active=4, chunk=48, solo_points=cut)
+    st = srv.run(reqs)
+    srv.close()
+    assert st.completed == len(mix) and st.peak_bytes <= budget
+    for r, tr in zip(reqs, solo):
+        assert np.array_equal(r.trace, tr), r.rid
+    big = [r for r in reqs if r.problem.npts >= cut]
+    assert len(big) >= 2
+    assert [r.rid for r in sorted(big, key=lambda r: r.done)] == [r.rid for r in big]
+
+
 def test_autotuner_picks_a_candidate():
     _torch()
     from paper_2106_11476_amd import serve
