@@ -192,6 +192,14 @@ struct fw2_domain {
 
 namespace {
 
+// The velocity sweeps record the receivers in an extra block of their
+// launch; the one-thread-per-point kernel leaves them to a launch of their own.
+void sync_receiver_args(fw2_domain *d)
+{
+    d->args.rcv = d->rcv;
+    if (d->kc.variant == 0) d->args.rcv.step = nullptr;
+}
+
 void drop_graph(fw2_domain *d)
 {
     if (d->graph) {
@@ -207,7 +215,7 @@ fw2_status enqueue_step(fw2_domain *d, TimingSlot *ts)
     FW2_HIP(fw2::launch_pressure(d->args, L, sch, d->kc, d->stream));
     if (ts) FW2_HIP(hipEventRecord(ts->ev[1], d->stream));
     FW2_HIP(fw2::launch_sources(d->src, d->stream));
-    FW2_HIP(fw2::launch_receivers(d->rcv, d->stream));
+    if (!d->args.rcv.step) FW2_HIP(fw2::launch_receivers(d->rcv, d->stream));
     if (ts) FW2_HIP(hipEventRecord(ts->ev[2], d->stream));
     FW2_HIP(fw2::launch_velocity(d->args, L, sch, d->kc, d->stream));
     if (ts) FW2_HIP(hipEventRecord(ts->ev[3], d->stream));
@@ -219,7 +227,7 @@ fw2_status enqueue_step_on(fw2_domain *d, hipStream_t s)
     const int L = d->desc.n_relax, sch = d->desc.relax_scheme;
     FW2_HIP(fw2::launch_pressure(d->args, L, sch, d->kc, s));
     FW2_HIP(fw2::launch_sources(d->src, s));
-    FW2_HIP(fw2::launch_receivers(d->rcv, s));
+    if (!d->args.rcv.step) FW2_HIP(fw2::launch_receivers(d->rcv, s));
     FW2_HIP(fw2::launch_velocity(d->args, L, sch, d->kc, s));
     return FW2_OK;
 }
@@ -499,6 +507,7 @@ fw2_status fw2_create_domain(const fw2_domain_desc *desc, void *dev_workspace, u
     d->src.geo = d->rcv.geo = g;
     d->src.p = d->rcv.p = a.p;
     d->src.step = d->rcv.step = d->counter;
+    sync_receiver_args(d);
     FW2_HIP_C(hipStreamSynchronize(d->stream));
 #undef FW2_HIP_C
     *out = d;
@@ -553,6 +562,7 @@ fw2_status fw2_add_receivers(fw2_domain *d, int32_t n_rcv, const int64_t *flat_i
     d->rcv.idx = flat_idx;
     d->rcv.trace = trace;
     d->rcv.cap = n_rcv > 0 ? cap_steps : 0;
+    sync_receiver_args(d);
     return FW2_OK;
 }
 

@@ -506,13 +506,43 @@ __global__ void __launch_bounds__(BX) pressure_sweep2d(const StepArgs a, int row
     pressure_tile2d<L, CENTRED, BX, PF, PP>(a, rows, (tile % nbx) * BX, (tile / nbx) * rows, sx, sy);
 }
 
+// Padded element offset of a flat unpadded index x + nx (y + ny z).
+__device__ __forceinline__ int64_t padded_index(const Geometry &g, int64_t f)
+{
+    const int64_t x = f % g.n[0];
+    const int64_t t = f / g.n[0];
+    const int64_t y = t % g.n[1];
+    const int64_t z = t / g.n[1];
+    return g.origin + z * g.plane + y * g.pitch + x;
+}
+
+// The receivers of the current step, recorded by one whole block, then the
+// device step counter advanced (one block, so no other block reads the
+// counter meanwhile).
+__device__ __forceinline__ void record_receivers(const SparseArgs &s)
+{
+    const long long step = *s.step;
+    if (step < s.cap)
+        for (int r = threadIdx.x; r < s.n; r += blockDim.x)
+            s.trace[step * s.n + r] = s.p[padded_index(s.geo, s.idx[r])];
+    __syncthreads();
+    if (threadIdx.x == 0) s.step[0] = step + 1;
+}
+
 template <int L, bool CENTRED, int BX, bool PF, bool PP>
 __global__ void __launch_bounds__(BX) velocity_sweep2d(const StepArgs a, int rows, int nbx, int nblocks)
 {
+    // with receivers, block 0 records them (dispatched first, it overlaps the
+    // tiles instead of trailing them) and blocks 1.. take the tiles
+    const int shift = a.rcv.step ? 1 : 0;
+    if ((int)blockIdx.x < shift) {
+        record_receivers(a.rcv);
+        return;
+    }
     __shared__ float sp[4][BX + 8];     // p rows, column c <-> x0 - 4 + c
     __shared__ float sr[3][BX + 1];     // rho rows, column c <-> x0 + c
     __shared__ float sk[3][BX + 1];     // kappa0 rows
-    const int tile = tile_of_block(blockIdx.x, nblocks);
+    const int tile = tile_of_block((int)blockIdx.x - shift, nblocks);
     velocity_tile2d<L, CENTRED, BX, PF, PP>(a, rows, (tile % nbx) * BX, (tile / nbx) * rows, sp, sr, sk);
 }
 
@@ -737,11 +767,17 @@ __global__ void __launch_bounds__(BX *BY) pressure_sweep3d(const StepArgs a, int
 template <int L, bool CENTRED, int BX, int BY, bool PP, bool PF>
 __global__ void __launch_bounds__(BX *BY) velocity_sweep3d(const StepArgs a, int rows, int nbx, int nby, int nblocks)
 {
+    // with receivers, block 0 records them and blocks 1.. take the tiles
+    const int shift = a.rcv.step ? 1 : 0;
+    if ((int)blockIdx.x < shift) {
+        record_receivers(a.rcv);
+        return;
+    }
     constexpr int NT = BX * BY;
     constexpr int PW = BX + 8, PH = BY + 8;     // p tile: halo 4 (x0-4.., y0-4..)
     constexpr int RW = BX + 1, RH = BY + 1;     // rho / kappa0 tiles: +1 halo
     const Geometry &g = a.geo;
-    const int tile = tile_of_block(blockIdx.x, nblocks);
+    const int tile = tile_of_block((int)blockIdx.x - shift, nblocks);
     const int tx_ = tile % nbx, rest = tile / nbx;
     const int x0 = tx_ * BX, y0 = (rest % nby) * BY, z0 = (rest / nby) * rows;
     const int tid = threadIdx.x;
@@ -889,15 +925,6 @@ __global__ void __launch_bounds__(BX *BY) velocity_sweep3d(const StepArgs a, int
     }
 }
 
-__device__ __forceinline__ int64_t padded_index(const Geometry &g, int64_t f)
-{
-    const int64_t x = f % g.n[0];
-    const int64_t t = f / g.n[0];
-    const int64_t y = t % g.n[1];
-    const int64_t z = t / g.n[1];
-    return g.origin + z * g.plane + y * g.pitch + x;
-}
-
 __global__ void source_kernel(const SparseArgs s)
 {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
@@ -912,12 +939,7 @@ __global__ void source_kernel(const SparseArgs s)
 // device step counter (single block, so no other block reads it meanwhile).
 __global__ void __launch_bounds__(256) receiver_kernel(const SparseArgs s)
 {
-    const long long step = *s.step;
-    if (step < s.cap)
-        for (int r = threadIdx.x; r < s.n; r += blockDim.x)
-            s.trace[step * s.n + r] = s.p[padded_index(s.geo, s.idx[r])];
-    __syncthreads();
-    if (threadIdx.x == 0) s.step[0] = step + 1;
+    record_receivers(s);
 }
 
 __global__ void fill_kernel(float *dst, int64_t n, float value)
@@ -953,7 +975,8 @@ hipError_t launch_sweep(const StepArgs &a, bool pressure, const KernelConfig &kc
         if (pressure)                                                                                   \
             hipLaunchKernelGGL((pressure_sweep2d<L, C, BXV, PF, PP>), dim3(nblocks), dim3(BXV), 0, st, a, kc.rows, nbx, nblocks); \
         else                                                                                            \
-            hipLaunchKernelGGL((velocity_sweep2d<L, C, BXV, PF, PP>), dim3(nblocks), dim3(BXV), 0, st, a, kc.rows, nbx, nblocks); \
+            hipLaunchKernelGGL((velocity_sweep2d<L, C, BXV, PF, PP>), dim3(nblocks + (a.rcv.step ? 1 : 0)), dim3(BXV), 0, st, \
+                               a, kc.rows, nbx, nblocks);                                                  \
         return hipGetLastError();                                                                       \
     }
     FW2_SWEEP(64)
@@ -976,7 +999,8 @@ hipError_t launch_sweep3(const StepArgs &a, bool pressure, const KernelConfig &k
             hipLaunchKernelGGL((pressure_sweep3d<L, C, BXV, BYV, PP, PF>), dim3(nblocks), dim3(BXV * BYV), 0, st, \
                                a, kc.rows, nbx, nby, nblocks);                                          \
         else                                                                                            \
-            hipLaunchKernelGGL((velocity_sweep3d<L, C, BXV, BYV, PP, PF>), dim3(nblocks), dim3(BXV * BYV), 0, st, \
+            hipLaunchKernelGGL((velocity_sweep3d<L, C, BXV, BYV, PP, PF>), dim3(nblocks + (a.rcv.step ? 1 : 0)),   \
+                               dim3(BXV * BYV), 0, st,                                                  \
                                a, kc.rows, nbx, nby, nblocks);                                          \
         return hipGetLastError();                                                                       \
     }

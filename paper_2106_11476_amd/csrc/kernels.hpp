@@ -30,6 +30,20 @@ struct Geometry {
     int64_t stride;          // elements between consecutive arrays
 };
 
+struct SparseArgs {
+    Geometry geo;
+    float *p;
+    long long *step;         // device step counter
+    const int64_t *idx;      // flat unpadded indices
+    const int32_t *sig;      // sources: signal of each point
+    const float *w;          // sources: weight of each point
+    const float *signals;    // sources: [n_sig][n_t]
+    float *trace;            // receivers: [cap][n]
+    int32_t n;               // points
+    int32_t n_t;             // sources: samples per signal
+    long long cap;           // receivers: trace rows
+};
+
 struct StepArgs {
     Geometry geo;
     float *p;
@@ -56,21 +70,12 @@ struct StepArgs {
     float pw[4][4];
     float g11s;
     float q2;
+    // Receivers recorded (and the step counter advanced) by one extra block
+    // of the velocity sweep launch, which reads p without writing it and runs
+    // after the sources; rcv.step == nullptr: a separate launch does it.
+    SparseArgs rcv;
 };
 
-struct SparseArgs {
-    Geometry geo;
-    float *p;
-    long long *step;         // device step counter
-    const int64_t *idx;      // flat unpadded indices
-    const int32_t *sig;      // sources: signal of each point
-    const float *w;          // sources: weight of each point
-    const float *signals;    // sources: [n_sig][n_t]
-    float *trace;            // receivers: [cap][n]
-    int32_t n;               // points
-    int32_t n_t;             // sources: samples per signal
-    long long cap;           // receivers: trace rows
-};
 
 // Kernel variant and tile shape.  variant 0: one thread per point over a
 // (64 x 8) tile, every stencil tap a cached global load (any ndim).
