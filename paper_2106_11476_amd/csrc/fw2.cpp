@@ -10,6 +10,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "kernels.hpp"
@@ -720,7 +721,7 @@ fw2_status fw2_adjoint_workspace_bytes(const fw2_domain *d, uint64_t *bytes)
     if (!d) return fail(FW2_E_STATE, "domain is NULL");
     if (!bytes) return fail(FW2_E_INVALID, "bytes is NULL");
     const int nd = d->desc.ndim;
-    *bytes = (uint64_t)(state_floats(d) + (int64_t)(4 + 4 * nd) * d->ly.geo.stride) * 4;
+    *bytes = (uint64_t)(state_floats(d) + (int64_t)(5 + 3 * nd) * d->ly.geo.stride) * 4;
     return FW2_OK;
 }
 
@@ -742,11 +743,11 @@ fw2_status fw2_adjoint_begin(fw2_domain *d, void *dev_workspace, uint64_t bytes)
     fw2::AdjointBuffers &b = d->adj;
     b.lp = base;
     b.pp = base + state_floats(d);
-    b.sS = b.pp + S;
+    b.pq = b.pp + S;
+    b.sS = b.pq + S;
     b.lDv = b.sS + S;
-    b.lpb = b.lDv + nd * S;
-    b.lkv = b.lpb + nd * S;
-    b.lDp = b.lkv + nd * S;
+    b.lqr = b.lDv + nd * S;
+    b.lDp = b.lqr + nd * S;
     b.gk = b.lDp + nd * S;
     b.out = b.gk + S;
     FW2_HIP(hipMemsetAsync(dev_workspace, 0, need, d->stream));
@@ -767,7 +768,10 @@ fw2_status fw2_adjoint_step(fw2_domain *d, const void *dev_state, const void *de
                                                   d->adj_pp_step == step, dev_residual, d->stream, &next);
     d->adj_pp_step = -1;
     FW2_HIP(e);
-    if (next) d->adj_pp_step = step - 1;
+    if (next) {                          // p'' of step - 1 is in the second buffer
+        std::swap(d->adj.pp, d->adj.pq);
+        d->adj_pp_step = step - 1;
+    }
     return FW2_OK;
 }
 

@@ -132,12 +132,13 @@ void prepare_batch_launches();
 // Discrete adjoint of one step (adjoint.hip): device arrays of the adjoint
 // state (same layout as the forward state block) and the per-step temporaries.
 struct AdjointBuffers {
-    float *lp, *pp, *sS, *lDv, *lpb, *lkv, *lDp, *gk, *out;
+    float *lp, *pp, *pq, *sS, *lDv, *lqr, *lDp, *gk, *out;
 };
 // One reverse step.  state: forward state block at the step's input;
 // state_prev: that of the step before, or nullptr.  have_pp: b.pp / b.sS
 // already hold this step's p'' and S (from the previous call); *pp_next is
-// set when they now hold those of step - 1.
+// set when b.pq / b.sS now hold those of step - 1 (the caller then swaps
+// b.pp and b.pq).
 hipError_t launch_adjoint_step(const StepArgs &f, const SparseArgs &src, const SparseArgs &rcv, int L,
                                const float *state, const float *state_prev, const AdjointBuffers &b,
                                long long step, bool have_pp, const float *residual, hipStream_t stream,
