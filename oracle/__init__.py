@@ -23,4 +23,7 @@ solver      Per-point coefficient maps and the time loop (C stepper in
             fw2_oracle.c, plus a vectorised NumPy twin for tiny grids).
 physics     Closed-form references used as pins (Green's function, exact
             pre-shock simple wave, power-law / Kramers-Kronig targets).
+adjoint     Discrete adjoint of the time-centred step (gradient of a trace
+            misfit with respect to c), pinned by central differences of the
+            stepper.
 """
