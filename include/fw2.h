@@ -83,7 +83,8 @@ enum { FW2_STENCIL_GLOBAL = 0, FW2_STENCIL_LOCAL = 1 };
 typedef struct {
     int32_t ndim;             /* 2 or 3 */
     int32_t n_relax;          /* L, 1..FW2_MAX_RELAX */
-    int64_t n[3];             /* nx, ny, nz including the boundary layers; nz = 1 in 2D */
+    int64_t n[3];             /* nx, ny, nz including the boundary layers; nz = 1 in 2D;
+                                 each 1..2^20, and in 3D (nx + 72)(ny + 8) < 2^29 */
     double h;                 /* grid step (m) */
     double dt;                /* time step (s) */
     int32_t bound_cells[3];   /* L_C-PML per side per axis, in cells (Sec. 3.3) */

@@ -57,7 +57,7 @@ fw2_status validate_scalars(const fw2_domain_desc *d)
     if (!d) return fail(FW2_E_INVALID, "desc is NULL");
     if (d->ndim != 2 && d->ndim != 3) return fail(FW2_E_INVALID, "ndim must be 2 or 3");
     if (d->n_relax < 1 || d->n_relax > FW2_MAX_RELAX)
-        return fail(FW2_E_INVALID, "n_relax must be in 1..4");
+        return fail(FW2_E_INVALID, "n_relax must be in 1..8");
     for (int a = 0; a < 3; ++a) {
         const int64_t na = d->n[a];
         if (a < d->ndim) {
@@ -70,6 +70,9 @@ fw2_status validate_scalars(const fw2_domain_desc *d)
             return fail(FW2_E_INVALID, "n[2] must be 1 in 2D");
         }
     }
+    // the 3D sweeps address a padded plane with 32-bit byte offsets
+    if (d->ndim == 3 && (d->n[0] + 72) * (d->n[1] + 8) >= ((int64_t)1 << 29))
+        return fail(FW2_E_INVALID, "a 3D plane (nx x ny) must hold fewer than 2^29 points");
     if (!finite_pos(d->h) || !finite_pos(d->dt)) return fail(FW2_E_INVALID, "h and dt must be positive");
     if (!(d->pml_Rc > 0.0 && d->pml_Rc < 1.0)) return fail(FW2_E_INVALID, "pml_Rc must be in (0, 1)");
     if (d->pml_npoly < 1 || d->pml_npoly > 8) return fail(FW2_E_INVALID, "pml_npoly must be in 1..8");

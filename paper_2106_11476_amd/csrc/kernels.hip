@@ -553,13 +553,50 @@ __global__ void __launch_bounds__(BX) velocity_sweep2d(const StepArgs a, int row
 // halos) are staged cooperatively into LDS rings, one barrier per plane.
 // ---------------------------------------------------------------------------
 
+// 3D arrays are several GB, so a per-lane element index needs 64 bits, and
+// a 64-bit address per lane and array costs two VGPRs each.  The 3D sweeps
+// instead address one plane at a time: a base that is uniform over the block
+// (scalar registers; the array, the plane and the (-1, -1) corner folded in)
+// plus a 32-bit per-lane byte offset within the plane, the scalar-base form
+// of the global loads and stores.  A plane holds fewer than 2^29 points
+// (checked when the domain is created), so the offsets fit.
+// Pointers into device global memory (address space 1), so that the
+// loads and stores through a rebuilt base keep the global forms.
+typedef const __attribute__((address_space(1))) char *gbase;
+typedef const __attribute__((address_space(1))) float *gcfloat;
+typedef __attribute__((address_space(1))) float *gfloat;
+
+template <typename T>
+__device__ __forceinline__ gbase plane_base(const T *f, const Geometry &g, int z)
+{
+    const int zz = (unsigned)z < (unsigned)g.n[2] ? z : -1;      // outside: the zero halo plane
+    const uint64_t u = reinterpret_cast<uint64_t>(f + (g.origin + (int64_t)zz * g.plane - g.pitch - 1));
+    // the same for every lane (z is uniform over the block): scalar registers
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+    return (gbase)(((uint64_t)hi << 32) | lo);
+}
+
+// Element offset of (x, y) from a plane base; outside the grid, the zero
+// halo point (-1, -1) of the same plane.
+__device__ __forceinline__ uint32_t plane_point(const Geometry &g, int x, int y)
+{
+    const bool in = (unsigned)x < (unsigned)g.n[0] && (unsigned)y < (unsigned)g.n[1];
+    return in ? (uint32_t)((y + 1) * (int)g.pitch + (x + 1)) : 0u;
+}
+
+__device__ __forceinline__ gcfloat at_plane(gbase base, uint32_t pt) { return (gcfloat)(base + pt * 4u); }
+__device__ __forceinline__ gfloat at_plane_w(gbase base, uint32_t pt) { return (gfloat)(base + pt * 4u); }
+__device__ __forceinline__ int label_at(gbase base, uint32_t pt)
+{
+    return (int)((const __attribute__((address_space(1))) uint8_t *)base)[pt];
+}
+__device__ __forceinline__ float ntld(gcfloat p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ void ntst(gfloat p, float v) { __builtin_nontemporal_store(v, p); }
+
 __device__ __forceinline__ float ldz3(const float *__restrict__ f, const Geometry &g, int x, int y, int z)
 {
-    const bool in = (unsigned)x < (unsigned)g.n[0] && (unsigned)y < (unsigned)g.n[1] &&
-                    (unsigned)z < (unsigned)g.n[2];
-    const int64_t o = in ? g.origin + (int64_t)z * g.plane + (int64_t)y * g.pitch + x
-                         : g.origin - g.plane - g.pitch - 1;
-    return f[o];
+    return *at_plane(plane_base(f, g, z), plane_point(g, x, y));
 }
 
 // Stage the (H x W) window of plane z whose (0, 0) is (xs, ys) into LDS.
@@ -623,6 +660,7 @@ __global__ void __launch_bounds__(BX *BY) pressure_sweep3d(const StepArgs a, int
     const int i = x0 + tx, j = y0 + ty;
     const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
     const bool live = i < nx && j < ny;
+    const uint32_t pt = plane_point(g, i, j);      // own point in its plane
     const float *__restrict__ vx = a.v;
     const float *__restrict__ vy = a.v + g.stride;
     const float *__restrict__ vz = a.v + 2 * g.stride;
@@ -659,16 +697,16 @@ __global__ void __launch_bounds__(BX *BY) pressure_sweep3d(const StepArgs a, int
         o.r0 = 1.0f;
         o.l = 0;
         if (live && k < nz) {
-            const int64_t idx = g.origin + (int64_t)k * g.plane + (int64_t)j * g.pitch + i;
-            o.p0 = a.p[idx];
-            o.k0 = a.kap[idx];
-            o.q0 = a.nlq[idx];
-            if (PP) o.r0 = a.rho[idx];
-            o.l = a.label ? (int)a.label[idx] : 0;
+            o.p0 = *at_plane(plane_base(a.p, g, k), pt);
+            o.k0 = *at_plane(plane_base(a.kap, g, k), pt);
+            o.q0 = *at_plane(plane_base(a.nlq, g, k), pt);
+            if (PP) o.r0 = *at_plane(plane_base(a.rho, g, k), pt);
+            o.l = a.label ? label_at(plane_base(a.label, g, k), pt) : 0;
 #pragma unroll
             for (int ax = 0; ax < 3; ++ax)
 #pragma unroll
-                for (int nu = 0; nu < L; ++nu) o.m[ax][nu] = ntld(&a.psi2[(int64_t)(ax * L + nu) * g.stride + idx]);
+                for (int nu = 0; nu < L; ++nu)
+                    o.m[ax][nu] = ntld(at_plane(plane_base(a.psi2 + (int64_t)(ax * L + nu) * g.stride, g, k), pt));
         }
     };
     Staged<XW, XH, NT> px;
@@ -699,7 +737,6 @@ __global__ void __launch_bounds__(BX *BY) pressure_sweep3d(const StepArgs a, int
             stage_load<ZW, ZH, NT>(pz, vz, g, x0 - 1, y0 - 1, k + 1, tid);
             load_own(cur, k + 1);
         }
-        const int64_t idx = g.origin + (int64_t)k * g.plane + (int64_t)j * g.pitch + i;
         const float p0 = o.p0, k0 = o.k0, q0 = o.q0, r0 = o.r0;
         const int l = o.l;
         float m[3][L];
@@ -755,11 +792,12 @@ __global__ void __launch_bounds__(BX *BY) pressure_sweep3d(const StepArgs a, int
                 S += Sa;
             }
             const float kappa = k0 * (1.0f + q0 * p0);
-            a.p[idx] = p0 - a.dt * S / kappa;
+            *at_plane_w(plane_base(a.p, g, k), pt) = p0 - a.dt * S / kappa;
 #pragma unroll
             for (int ax = 0; ax < 3; ++ax)
 #pragma unroll
-                for (int nu = 0; nu < L; ++nu) ntst(&a.psi2[(int64_t)(ax * L + nu) * g.stride + idx], m[ax][nu]);
+                for (int nu = 0; nu < L; ++nu)
+                    ntst(at_plane_w(plane_base(a.psi2 + (int64_t)(ax * L + nu) * g.stride, g, k), pt), m[ax][nu]);
         }
     }
 }
@@ -785,6 +823,7 @@ __global__ void __launch_bounds__(BX *BY) velocity_sweep3d(const StepArgs a, int
     const int i = x0 + tx, j = y0 + ty;
     const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
     const bool live = i < nx && j < ny;
+    const uint32_t pt = plane_point(g, i, j);      // own point in its plane
     const float *__restrict__ pp = a.p;
 
     __shared__ float sp[4][PH * PW];
@@ -813,14 +852,14 @@ __global__ void __launch_bounds__(BX *BY) velocity_sweep3d(const StepArgs a, int
         o.u[0] = o.u[1] = o.u[2] = 0.0f;
         o.l = 0;
         if (live && k < nz) {
-            const int64_t idx = g.origin + (int64_t)k * g.plane + (int64_t)j * g.pitch + i;
 #pragma unroll
-            for (int ax = 0; ax < 3; ++ax) o.u[ax] = a.v[(int64_t)ax * g.stride + idx];
-            o.l = a.label ? (int)a.label[idx] : 0;
+            for (int ax = 0; ax < 3; ++ax) o.u[ax] = *at_plane(plane_base(a.v + (int64_t)ax * g.stride, g, k), pt);
+            o.l = a.label ? label_at(plane_base(a.label, g, k), pt) : 0;
 #pragma unroll
             for (int ax = 0; ax < 3; ++ax)
 #pragma unroll
-                for (int nu = 0; nu < L; ++nu) o.m[ax][nu] = ntld(&a.psi1[(int64_t)(ax * L + nu) * g.stride + idx]);
+                for (int nu = 0; nu < L; ++nu)
+                    o.m[ax][nu] = ntld(at_plane(plane_base(a.psi1 + (int64_t)(ax * L + nu) * g.stride, g, k), pt));
         }
     };
     Staged<PW, PH, NT> ps;
@@ -850,7 +889,6 @@ __global__ void __launch_bounds__(BX *BY) velocity_sweep3d(const StepArgs a, int
             stage_load<RW, RH, NT>(ks, a.kap, g, x0, y0, k + 2, tid);
             load_own(cur, k + 1);
         }
-        const int64_t idx = g.origin + (int64_t)k * g.plane + (int64_t)j * g.pitch + i;
         const float u[3] = {o.u[0], o.u[1], o.u[2]};
         const int l = o.l;
         float m[3][L];
@@ -917,9 +955,11 @@ __global__ void __launch_bounds__(BX *BY) velocity_sweep3d(const StepArgs a, int
                     S += CENTRED ? m[ax][nu] : mn;
                     m[ax][nu] = mn;
                 }
-                a.v[(int64_t)ax * g.stride + idx] = u[ax] - a.dt * S / (rho_a * (1.0f + kap_a * pbar));
+                *at_plane_w(plane_base(a.v + (int64_t)ax * g.stride, g, k), pt) =
+                    u[ax] - a.dt * S / (rho_a * (1.0f + kap_a * pbar));
 #pragma unroll
-                for (int nu = 0; nu < L; ++nu) ntst(&a.psi1[(int64_t)(ax * L + nu) * g.stride + idx], m[ax][nu]);
+                for (int nu = 0; nu < L; ++nu)
+                    ntst(at_plane_w(plane_base(a.psi1 + (int64_t)(ax * L + nu) * g.stride, g, k), pt), m[ax][nu]);
             }
         }
     }
