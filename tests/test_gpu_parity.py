@@ -289,6 +289,31 @@ def test_split_steps_graph_and_direct_are_bitwise_equal():
     assert np.array_equal(ta, tb) and np.array_equal(ta, tc)
 
 
+def test_moving_a_domain_between_streams_is_bitwise():
+    """fw2_set_stream: steps split over two streams (the domain moved between
+    them, graph chunks included) end bitwise where one stream ends."""
+    torch = _torch()
+    from paper_2106_11476_amd import fw2
+    prob = W.plain_2d(interior=120, n_steps=200, n_rcv=8)
+    _say("stream move 216x216")
+    a, ta, _ = gpu_run(prob, 200)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    dom = fw2.from_problem(prob, device="cuda:0", stream=s1, cap_steps=200)
+    dom.step(70)
+    dom.set_stream(s2)
+    dom.step(90)
+    dom.set_stream(s1)
+    dom.step(40)
+    s1.synchronize()
+    assert dom.current_step() == 200
+    f = dom.read_fields(fw2.FIELD_ALL)
+    tr = dom.trace.cpu().numpy()
+    dom.destroy_domain()
+    for k in a:
+        assert np.array_equal(a[k], f[k]), k
+    assert np.array_equal(ta, tr)
+
+
 def test_checkpoint_resume_is_bitwise():
     torch = _torch()
     from paper_2106_11476_amd import fw2
