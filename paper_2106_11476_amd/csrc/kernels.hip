@@ -202,14 +202,46 @@ __device__ __forceinline__ int tile_of_block(int bid, int nblocks)
     return (bid % 8) * (nblocks / 8) + bid / 8;
 }
 
-// Value of a padded array at (x, y): inside the grid the sample itself, else
-// the halo cell (-1, -1), which is zero in every array (never written), so
-// the load is branch-free.
-__device__ __forceinline__ float ldz(const float *__restrict__ f, const Geometry &g, int x, int y)
+// Pointers into device global memory (address space 1), so that the
+// loads and stores through a rebuilt base keep the global forms.
+typedef const __attribute__((address_space(1))) char *gbase;
+typedef const __attribute__((address_space(1))) float *gcfloat;
+typedef __attribute__((address_space(1))) float *gfloat;
+
+template <typename T>
+__device__ __forceinline__ gbase plane_base(const T *f, const Geometry &g, int z)
+{
+    const int zz = (unsigned)z < (unsigned)g.n[2] ? z : -1;      // outside: the zero halo plane
+    const uint64_t u = reinterpret_cast<uint64_t>(f + (g.origin + (int64_t)zz * g.plane - g.pitch - 1));
+    // the same for every lane (z is uniform over the block): scalar registers
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+    return (gbase)(((uint64_t)hi << 32) | lo);
+}
+
+// Element offset of (x, y) from a plane base; outside the grid, the zero
+// halo point (-1, -1) of the same plane.
+__device__ __forceinline__ uint32_t plane_point(const Geometry &g, int x, int y)
 {
     const bool in = (unsigned)x < (unsigned)g.n[0] && (unsigned)y < (unsigned)g.n[1];
-    const int64_t o = in ? g.origin + (int64_t)y * g.pitch + x : g.origin - g.pitch - 1;
-    return f[o];
+    return in ? (uint32_t)((y + 1) * (int)g.pitch + (x + 1)) : 0u;
+}
+
+__device__ __forceinline__ gcfloat at_plane(gbase base, uint32_t pt) { return (gcfloat)(base + pt * 4u); }
+__device__ __forceinline__ gfloat at_plane_w(gbase base, uint32_t pt) { return (gfloat)(base + pt * 4u); }
+__device__ __forceinline__ int label_at(gbase base, uint32_t pt)
+{
+    return (int)((const __attribute__((address_space(1))) uint8_t *)base)[pt];
+}
+__device__ __forceinline__ float ntld(gcfloat p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ void ntst(gfloat p, float v) { __builtin_nontemporal_store(v, p); }
+
+// Value of a padded 2D array at (x, y): inside the grid the sample itself,
+// else the halo cell (-1, -1), which is zero in every array (never written),
+// so the load is branch-free.  A 2D array is one plane (z = 0).
+__device__ __forceinline__ float ldz(const float *__restrict__ f, const Geometry &g, int x, int y)
+{
+    return *at_plane(plane_base(f, g, 0), plane_point(g, x, y));
 }
 
 // LDS hand-off between the threads of a block.  A one-wavefront block needs
@@ -253,17 +285,18 @@ __device__ __forceinline__ void p_load_row(PRow<L> &r, const StepArgs &a, int i,
     r.vxn = ldz(vx, g, i, j + 1);
     r.hx = t < 8 ? ldz(vx, g, halo_x<BX>(t, x0), j + 1) : 0.0f;
     r.hy = t < 2 ? ldz(vy, g, t == 0 ? x0 - 1 : x0 + BX, j) : 0.0f;
-    const int64_t idx = g.origin + (int64_t)j * g.pitch + i;
+    const uint32_t pt = plane_point(g, i, j);
     if (live) {
-        r.p0 = a.p[idx];
-        r.k0 = a.kap[idx];
-        r.q0 = a.nlq[idx];
-        r.r0 = PP ? a.rho[idx] : 1.0f;
-        r.l = a.label ? (int)a.label[idx] : 0;
+        r.p0 = *at_plane(plane_base(a.p, g, 0), pt);
+        r.k0 = *at_plane(plane_base(a.kap, g, 0), pt);
+        r.q0 = *at_plane(plane_base(a.nlq, g, 0), pt);
+        r.r0 = PP ? *at_plane(plane_base(a.rho, g, 0), pt) : 1.0f;
+        r.l = a.label ? label_at(plane_base(a.label, g, 0), pt) : 0;
 #pragma unroll
         for (int ax = 0; ax < 2; ++ax)
 #pragma unroll
-            for (int nu = 0; nu < L; ++nu) r.m[ax][nu] = ntld(&a.psi2[(int64_t)(ax * L + nu) * g.stride + idx]);
+            for (int nu = 0; nu < L; ++nu)
+                r.m[ax][nu] = ntld(at_plane(plane_base(a.psi2 + (int64_t)(ax * L + nu) * g.stride, g, 0), pt));
     }
 }
 
@@ -342,13 +375,14 @@ __device__ __forceinline__ void pressure_tile2d(const StepArgs &a, int rows, int
                 }
                 S += Sa;
             }
-            const int64_t idx = g.origin + (int64_t)j * g.pitch + i;
+            const uint32_t pt = plane_point(g, i, j);
             const float kappa = cur.k0 * (1.0f + cur.q0 * cur.p0);
-            pp[idx] = cur.p0 - a.dt * S / kappa;
+            *at_plane_w(plane_base(pp, g, 0), pt) = cur.p0 - a.dt * S / kappa;
 #pragma unroll
             for (int ax = 0; ax < 2; ++ax)
 #pragma unroll
-                for (int nu = 0; nu < L; ++nu) ntst(&psi[(int64_t)(ax * L + nu) * g.stride + idx], cur.m[ax][nu]);
+                for (int nu = 0; nu < L; ++nu)
+                    ntst(at_plane_w(plane_base(psi + (int64_t)(ax * L + nu) * g.stride, g, 0), pt), cur.m[ax][nu]);
         }
         if (PF) cur = nxt;
     }
@@ -372,15 +406,16 @@ __device__ __forceinline__ void v_load_row(VRow<L> &r, const StepArgs &a, int i,
     r.hp = t < 8 ? ldz(a.p, g, halo_x<BX>(t, x0), j + 1) : 0.0f;
     r.hr = t == 0 ? ldz(a.rho, g, x0 + BX, j + 1) : 0.0f;
     r.hk = t == 0 ? ldz(a.kap, g, x0 + BX, j + 1) : 0.0f;
-    const int64_t idx = g.origin + (int64_t)j * g.pitch + i;
+    const uint32_t pt = plane_point(g, i, j);
     if (live) {
-        r.ux = a.v[idx];
-        r.uy = a.v[g.stride + idx];
-        r.l = a.label ? (int)a.label[idx] : 0;
+        r.ux = *at_plane(plane_base(a.v, g, 0), pt);
+        r.uy = *at_plane(plane_base(a.v + g.stride, g, 0), pt);
+        r.l = a.label ? label_at(plane_base(a.label, g, 0), pt) : 0;
 #pragma unroll
         for (int ax = 0; ax < 2; ++ax)
 #pragma unroll
-            for (int nu = 0; nu < L; ++nu) r.m[ax][nu] = ntld(&a.psi1[(int64_t)(ax * L + nu) * g.stride + idx]);
+            for (int nu = 0; nu < L; ++nu)
+                r.m[ax][nu] = ntld(at_plane(plane_base(a.psi1 + (int64_t)(ax * L + nu) * g.stride, g, 0), pt));
     }
 }
 
@@ -436,7 +471,7 @@ __device__ __forceinline__ void velocity_tile2d(const StepArgs &a, int rows, int
         }
         lds_sync<BX>();
         if (live) {
-            const int64_t idx = g.origin + (int64_t)j * g.pitch + i;
+            const uint32_t pt = plane_point(g, i, j);
             const float *r0 = sp[j & 3], *rp = sp[(j + 1) & 3], *rm = sp[(j + 3) & 3];
             const float *rr0 = sr[j % 3], *kk0 = sk[j % 3];
             const float s0 = PP ? cell_r2(a, rr0[t], kk0[t]) : 0.0f;
@@ -461,9 +496,10 @@ __device__ __forceinline__ void velocity_tile2d(const StepArgs &a, int rows, int
                 const float pbar = 0.5f * (r0[t + 4] + r0[t + 5]);
                 const float rho_a = 0.5f * (rr0[t] + rr0[t + 1]);
                 const float kap_a = 0.5f * (kk0[t] + kk0[t + 1]);
-                vx[idx] = cur.ux - a.dt * S / (rho_a * (1.0f + kap_a * pbar));
+                *at_plane_w(plane_base(vx, g, 0), pt) = cur.ux - a.dt * S / (rho_a * (1.0f + kap_a * pbar));
 #pragma unroll
-                for (int nu = 0; nu < L; ++nu) ntst(&psi[(int64_t)nu * g.stride + idx], cur.m[0][nu]);
+                for (int nu = 0; nu < L; ++nu)
+                    ntst(at_plane_w(plane_base(psi + (int64_t)nu * g.stride, g, 0), pt), cur.m[0][nu]);
             }
             // v_y at (i, j + 1/2)
             if (j < ny - 1) {
@@ -488,9 +524,10 @@ __device__ __forceinline__ void velocity_tile2d(const StepArgs &a, int rows, int
                 const float pbar = 0.5f * (w[3] + w[4]);
                 const float rho_a = 0.5f * (rr0[t] + sr[(j + 1) % 3][t]);
                 const float kap_a = 0.5f * (kk0[t] + sk[(j + 1) % 3][t]);
-                vy[idx] = cur.uy - a.dt * S / (rho_a * (1.0f + kap_a * pbar));
+                *at_plane_w(plane_base(vy, g, 0), pt) = cur.uy - a.dt * S / (rho_a * (1.0f + kap_a * pbar));
 #pragma unroll
-                for (int nu = 0; nu < L; ++nu) ntst(&psi[(int64_t)(L + nu) * g.stride + idx], cur.m[1][nu]);
+                for (int nu = 0; nu < L; ++nu)
+                    ntst(at_plane_w(plane_base(psi + (int64_t)(L + nu) * g.stride, g, 0), pt), cur.m[1][nu]);
             }
         }
         if (PF) cur = nxt;
@@ -560,40 +597,6 @@ __global__ void __launch_bounds__(BX) velocity_sweep2d(const StepArgs a, int row
 // plus a 32-bit per-lane byte offset within the plane, the scalar-base form
 // of the global loads and stores.  A plane holds fewer than 2^29 points
 // (checked when the domain is created), so the offsets fit.
-// Pointers into device global memory (address space 1), so that the
-// loads and stores through a rebuilt base keep the global forms.
-typedef const __attribute__((address_space(1))) char *gbase;
-typedef const __attribute__((address_space(1))) float *gcfloat;
-typedef __attribute__((address_space(1))) float *gfloat;
-
-template <typename T>
-__device__ __forceinline__ gbase plane_base(const T *f, const Geometry &g, int z)
-{
-    const int zz = (unsigned)z < (unsigned)g.n[2] ? z : -1;      // outside: the zero halo plane
-    const uint64_t u = reinterpret_cast<uint64_t>(f + (g.origin + (int64_t)zz * g.plane - g.pitch - 1));
-    // the same for every lane (z is uniform over the block): scalar registers
-    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
-    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
-    return (gbase)(((uint64_t)hi << 32) | lo);
-}
-
-// Element offset of (x, y) from a plane base; outside the grid, the zero
-// halo point (-1, -1) of the same plane.
-__device__ __forceinline__ uint32_t plane_point(const Geometry &g, int x, int y)
-{
-    const bool in = (unsigned)x < (unsigned)g.n[0] && (unsigned)y < (unsigned)g.n[1];
-    return in ? (uint32_t)((y + 1) * (int)g.pitch + (x + 1)) : 0u;
-}
-
-__device__ __forceinline__ gcfloat at_plane(gbase base, uint32_t pt) { return (gcfloat)(base + pt * 4u); }
-__device__ __forceinline__ gfloat at_plane_w(gbase base, uint32_t pt) { return (gfloat)(base + pt * 4u); }
-__device__ __forceinline__ int label_at(gbase base, uint32_t pt)
-{
-    return (int)((const __attribute__((address_space(1))) uint8_t *)base)[pt];
-}
-__device__ __forceinline__ float ntld(gcfloat p) { return __builtin_nontemporal_load(p); }
-__device__ __forceinline__ void ntst(gfloat p, float v) { __builtin_nontemporal_store(v, p); }
-
 __device__ __forceinline__ float ldz3(const float *__restrict__ f, const Geometry &g, int x, int y, int z)
 {
     return *at_plane(plane_base(f, g, z), plane_point(g, x, y));
