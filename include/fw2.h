@@ -36,7 +36,7 @@ typedef enum {
     FW2_E_HIP = 3,          /* a HIP runtime call failed */
     FW2_E_STATE = 4,        /* call not valid in the domain's current state */
     FW2_E_UNSTABLE = 5,     /* watchdog found a non-finite or runaway field */
-    FW2_E_UNSUPPORTED = 6   /* valid request this build does not implement */
+    FW2_E_UNSUPPORTED = 6   /* valid request the library does not implement */
 } fw2_status;
 
 #define FW2_MAX_RELAX 8     /* largest number of relaxation mechanisms L */
