@@ -926,7 +926,7 @@ fw2_status fw2_batch_set_domains(fw2_batch *b, int32_t n, fw2_domain *const *dom
     fw2::BatchTable &T = b->host;
     std::memset(&T, 0, sizeof(T));
     T.rows = b->rows;
-    int tiles = 0, srcs = 0;
+    int tiles = 0;
     unsigned classes = 0;
     for (int32_t k = 0; k < n; ++k) {
         fw2_domain *d = domains[k];
@@ -944,15 +944,12 @@ fw2_status fw2_batch_set_domains(fw2_batch *b, int32_t n, fw2_domain *const *dom
         const int nby = (d->ly.geo.n[1] + b->rows - 1) / b->rows;
         e.tiles = nbx * nby;
         e.tile_base = tiles;
-        e.src_base = srcs;
         tiles += e.tiles;
-        srcs += d->src.n;
         b->doms.push_back(d);
         b->target.push_back(n_steps[k]);
     }
     T.n = n;
     T.total_tiles = tiles;
-    T.total_src = srcs;
     if (classes != b->classes) batch_drop_graph(b);    // the captured launches differ
     b->classes = classes;
     FW2_HIP(hipMemcpyAsync(b->dev, &T, sizeof(T), hipMemcpyHostToDevice, b->stream));

@@ -1140,29 +1140,21 @@ __global__ void __launch_bounds__(BX) batch_phase(const BatchTable *__restrict__
     }
 }
 
-__global__ void batch_sources(const BatchTable *__restrict__ T)
-{
-    const int total = T->total_src;
-    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < total; q += gridDim.x * blockDim.x) {
-        int d = 0;
-        for (int k = 1; k < T->n; ++k)
-            if (T->e[k].src_base <= q) d = k;
-        const BatchEntry &e = T->e[d];
-        const long long step = *e.src.step;
-        if (step >= e.n_steps || step >= e.src.n_t) continue;
-        const int lq = q - e.src_base;
-        const int64_t pi = padded_index(e.src.geo, e.src.idx[lq]);
-        e.src.p[pi] = e.src.p[pi] + e.src.w[lq] * e.src.signals[(int64_t)e.src.sig[lq] * e.src.n_t + step];
-    }
-}
-
-// One block per entry: record its receivers, then advance its counter.
-__global__ void __launch_bounds__(256) batch_receivers(const BatchTable *__restrict__ T)
+// One block per entry: its sources of the current step, then (after the
+// block barrier, so the receivers see them) its receivers, then its step
+// counter advanced.
+__global__ void __launch_bounds__(256) batch_sparse(const BatchTable *__restrict__ T)
 {
     const int d = blockIdx.x;
     if (d >= T->n) return;
     const BatchEntry &e = T->e[d];
-    const long long step = *e.rcv.step;
+    const long long step = *e.rcv.step;             // the entry's one counter (sources share it)
+    if (step < e.n_steps && step < e.src.n_t)
+        for (int q = threadIdx.x; q < e.src.n; q += blockDim.x) {
+            const int64_t pi = padded_index(e.src.geo, e.src.idx[q]);
+            e.src.p[pi] = e.src.p[pi] + e.src.w[q] * e.src.signals[(int64_t)e.src.sig[q] * e.src.n_t + step];
+        }
+    __syncthreads();
     if (step < e.n_steps && step < e.rcv.cap)
         for (int r = threadIdx.x; r < e.rcv.n; r += blockDim.x)
             e.rcv.trace[step * e.rcv.n + r] = e.rcv.p[padded_index(e.rcv.geo, e.rcv.idx[r])];
@@ -1301,8 +1293,7 @@ void launch_batch_phase(const BatchTable *T, int bx, unsigned classes, hipStream
 hipError_t launch_batch_step(const BatchTable *T, int n_entries_max, int bx, unsigned classes, hipStream_t st)
 {
     launch_batch_phase<true>(T, bx, classes, st);
-    hipLaunchKernelGGL(batch_sources, dim3(256), dim3(256), 0, st, T);
-    hipLaunchKernelGGL(batch_receivers, dim3(n_entries_max), dim3(256), 0, st, T);
+    hipLaunchKernelGGL(batch_sparse, dim3(n_entries_max), dim3(256), 0, st, T);
     launch_batch_phase<false>(T, bx, classes, st);
     return hipGetLastError();
 }

@@ -103,13 +103,11 @@ struct BatchEntry {
     long long n_steps;
     int32_t L, scheme;
     int32_t tile_base, tiles;        // tiles of bx columns x rows
-    int32_t src_base;                // first index in the flattened source list
 };
 
 struct BatchTable {
     int32_t n;
     int32_t total_tiles;
-    int32_t total_src;
     int32_t rows;                    // tile rows; tile columns bx = 64 or 256
     BatchEntry e[kMaxBatch];
 };
