@@ -97,10 +97,12 @@ def kernel_bytes(ndim, L, labels):
     return p_b, v_b, step_b
 
 
-def make_workload(name, n3d=1024):
+def make_workload(name, n3d=1024, relax=4):
     import workloads as W
+    if relax != 4 and name != "abdominal_2d":
+        raise SystemExit("--relax applies to the abdominal_2d workload only")
     if name == "abdominal_2d":
-        return W.abdominal_2d()
+        return W.abdominal_2d(L=relax)
     if name == "plain_2d":
         return W.plain_2d()
     if name == "skull_3d":
@@ -322,7 +324,7 @@ def summarize_stats_only(stats_db, name, title, commands):
         fh.write("\n".join(lines) + "\n")
 
 
-def summarize_profiles(stats_db, fetch_db, write_db, workload, copy_bytes, commands, n3d=1024):
+def summarize_profiles(stats_db, fetch_db, write_db, workload, copy_bytes, commands, n3d=1024, relax=4):
     """Write profiles/*.txt from rocprofv3 results (kernel-trace stats and the
     FETCH_SIZE / WRITE_SIZE passes).  Counter values are KiB per dispatch;
     each is scaled by what it reads for the plain copy that reads and writes
@@ -338,17 +340,19 @@ def summarize_profiles(stats_db, fetch_db, write_db, workload, copy_bytes, comma
     w_scale = copy_bytes / 1024.0 / wmax[copy_name][2]
     sha = kernel_source_sha()
     os.makedirs(PROFILES, exist_ok=True)
+    prob = make_workload(workload, n3d, relax)
     lines = ["rocprofv3 kernel statistics of the first command (benchmark workload %s; "
-             "kernels of the other legs that command runs are listed too)" % workload, "commands:"]
+             "kernels of the other legs that command runs are listed too)" % prob.name, "commands:"]
     lines += ["  " + c for c in commands]
     lines.append("kernel_source_sha256_16: %s" % sha)
     lines.append("%-70s %8s %12s %10s" % ("kernel", "calls", "total_us", "avg_us"))
     for name, calls, tot, avg in stats:
         lines.append("%-70s %8d %12.1f %10.3f" % (name[:70], calls, tot, avg))
     name = workload if workload != "skull_3d" else "skull_3d_%d" % n3d
+    if relax != 4:
+        name += "_L%d" % relax
     with open(os.path.join(PROFILES, "kernel_stats_%s.txt" % name), "w") as fh:
         fh.write("\n".join(lines) + "\n")
-    prob = make_workload(workload, n3d)
     labels = prob.label is not None and np.asarray(prob.relax_table).shape[0] > 1
     p_b, v_b, _ = kernel_bytes(prob.ndim, prob.n_relax, labels)
     # the benchmark's sweep kernels carry the mechanism count as their first
@@ -363,7 +367,7 @@ def summarize_profiles(stats_db, fetch_db, write_db, workload, copy_bytes, comma
         hbm = int(round((fk * f_scale + wk * w_scale) * 1024))
         algb = alg * prob.npts
         avg_us = [r[3] for r in stats if r[0] == n]
-        txt = ["HBM traffic of %s on workload %s" % (n, workload), "commands:"]
+        txt = ["HBM traffic of %s on workload %s" % (n, prob.name), "commands:"]
         txt += ["  " + c for c in commands]
         txt += ["kernel_source_sha256_16: %s" % sha,
                 "dispatches_counted: %d" % fmax[n][3],
@@ -447,6 +451,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--workload", default="abdominal_2d")
     ap.add_argument("--n3d", type=int, default=1024, help="cube side of the skull_3d workload")
+    ap.add_argument("--relax", type=int, default=4,
+                    help="relaxation mechanisms of the abdominal_2d workload (1..8 where fits exist)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true", help="skip the batched-serving leg")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint (gradient) leg")
@@ -475,7 +481,7 @@ def main():
         summarize_stats_only(*args.summarize_stats, commands=args.commands)
         return
     if args.summarize:
-        summarize_profiles(*args.summarize, workload=args.workload, n3d=args.n3d, copy_bytes=args.copy_read_bytes,
+        summarize_profiles(*args.summarize, workload=args.workload, n3d=args.n3d, relax=args.relax, copy_bytes=args.copy_read_bytes,
                            commands=args.commands)
         return
     if args.gpus != 1:
@@ -490,7 +496,7 @@ def main():
     copy_probe = None
     if args.copy_probe_mib > 0:
         copy_probe = probe_copy(torch, dev, args.copy_probe_mib)
-    prob = make_workload(args.workload, args.n3d)
+    prob = make_workload(args.workload, args.n3d, args.relax)
     K, Wm = int(args.steps), int(args.warmup)
     stream = torch.cuda.Stream(device=dev)
     dom = fw2.from_problem(prob, device=dev, stream=stream, cap_steps=K + Wm)

@@ -139,6 +139,23 @@ def test_heterogeneous_2d_full_size_random_state():
     compare(f, tr, ref, rtr, "abdominal_2d_full", prob=prob)
 
 
+def test_heterogeneous_2d_eight_mechanisms():
+    """The same recipe with L = 8 (fitted 8-mechanism tuples per layer): on a
+    320 x 224 grid for 1200 steps, and on the full 4096 x 2048 grid from a
+    seeded random state in the benchmark's launch configuration."""
+    prob = W.abdominal_2d(nx=320, ny=224, n_steps=1200, n_scatter=2000, L=8)
+    _say("abdominal_2d 320x224 L=8 1200 steps")
+    f, tr, _ = gpu_run(prob, prob.n_steps)
+    ref, rtr = oracle_run(prob, prob.n_steps)
+    compare(f, tr, ref, rtr, "abdominal_2d_small_L8", prob=prob)
+    prob = W.abdominal_2d(L=8)
+    st = _state(prob, 22)
+    _say("abdominal_2d 4096x2048 L=8 random state, 4 steps (graph chunk 2)")
+    f, tr, _ = gpu_run(prob, 4, state=st, graph_chunk=2)
+    ref, rtr = oracle_run(prob, 4, state=st)
+    compare(f, tr, ref, rtr, "abdominal_2d_full_L8", prob=prob)
+
+
 # -------------------------------------------------------- random states ---
 
 @pytest.mark.parametrize("shape,L,scheme,labels", [

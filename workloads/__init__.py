@@ -256,7 +256,13 @@ def abdominal_2d(nx=4096, ny=2048, seed=2, n_steps=12000, ppw=12, f0=3e6, cfl=0.
     beta_l = rng.uniform(3.5, 5.5, n_layers)
     a0_l = [ALPHA0_GRID[i] for i in rng.integers(0, len(ALPHA0_GRID), n_layers)]
     y_l = [Y_GRID[i] for i in rng.integers(0, len(Y_GRID), n_layers)]
-    rows = [tissue_row(a0_l[k], y_l[k], L, 3e6) for k in range(n_layers)]
+    if L <= 4:
+        rows = [tissue_row(a0_l[k], y_l[k], L, 3e6) for k in range(n_layers)]
+    else:
+        # 5..8 mechanisms are fitted for two laws only: fat layers take
+        # 0.5 dB/MHz/cm, muscle and connective layers 1.5 dB/MHz^1.3/cm
+        rows = [tissue_row(0.5, 1.0, L, 3e6) if classes[k] == 0 else tissue_row(1.5, 1.3, L, 3e6)
+                for k in range(n_layers)]
     c = c_l[layer].astype(np.float32)
     rho = rho_l[layer].astype(np.float32)
     beta = beta_l[layer].astype(np.float32)
@@ -270,7 +276,7 @@ def abdominal_2d(nx=4096, ny=2048, seed=2, n_steps=12000, ppw=12, f0=3e6, cfl=0.
     prob = Problem(shape=(nx, ny), h=h, dt=dt, n_relax=L, c=c, rho=rho, beta=beta,
                    relax_table=np.asarray(rows, np.float64), label=label,
                    bound_cells=(nb, nb), trans_cells=(ntr, ntr), n_steps=n_steps,
-                   name="abdominal_2d_%dx%d" % (nx, ny))
+                   name="abdominal_2d_%dx%d" % (nx, ny) + ("" if L == 4 else "_L%d" % L))
     prob.meta = {"classes": classes.tolist(), "alpha0": a0_l, "y": y_l}
     # linear array: pitch 12 cells (~ lambda), element width 10 cells, 8 cells
     # below the top boundary layer; fewer elements if the grid is narrow
