@@ -97,17 +97,16 @@ def kernel_bytes(ndim, L, labels):
     return p_b, v_b, step_b
 
 
-def make_workload(name, n3d=1024, relax=4):
+def make_workload(name, n3d=1024, relax=None):
+    """relax: mechanism count, None for the workload's own (4 in 2D, 2 in 3D)."""
     import workloads as W
-    if relax != 4 and name != "abdominal_2d":
-        raise SystemExit("--relax applies to the abdominal_2d workload only")
     if name == "abdominal_2d":
-        return W.abdominal_2d(L=relax)
-    if name == "plain_2d":
+        return W.abdominal_2d(L=4 if relax is None else relax)
+    if name == "plain_2d" and relax is None:
         return W.plain_2d()
     if name == "skull_3d":
-        return W.skull_3d(n=n3d)
-    raise SystemExit("unknown workload %s" % name)
+        return W.skull_3d(n=n3d, L=2 if relax is None else relax)
+    raise SystemExit("unknown workload %s, or one without a --relax option" % name)
 
 
 def cpu_baseline(prob, target_s=15.0):
@@ -324,7 +323,7 @@ def summarize_stats_only(stats_db, name, title, commands):
         fh.write("\n".join(lines) + "\n")
 
 
-def summarize_profiles(stats_db, fetch_db, write_db, workload, copy_bytes, commands, n3d=1024, relax=4):
+def summarize_profiles(stats_db, fetch_db, write_db, workload, copy_bytes, commands, n3d=1024, relax=None):
     """Write profiles/*.txt from rocprofv3 results (kernel-trace stats and the
     FETCH_SIZE / WRITE_SIZE passes).  Counter values are KiB per dispatch;
     each is scaled by what it reads for the plain copy that reads and writes
@@ -348,9 +347,10 @@ def summarize_profiles(stats_db, fetch_db, write_db, workload, copy_bytes, comma
     lines.append("%-70s %8s %12s %10s" % ("kernel", "calls", "total_us", "avg_us"))
     for name, calls, tot, avg in stats:
         lines.append("%-70s %8d %12.1f %10.3f" % (name[:70], calls, tot, avg))
-    name = workload if workload != "skull_3d" else "skull_3d_%d" % n3d
-    if relax != 4:
-        name += "_L%d" % relax
+    if workload == "skull_3d":
+        name = prob.name
+    else:
+        name = workload + ("" if prob.n_relax == 4 else "_L%d" % prob.n_relax)
     with open(os.path.join(PROFILES, "kernel_stats_%s.txt" % name), "w") as fh:
         fh.write("\n".join(lines) + "\n")
     labels = prob.label is not None and np.asarray(prob.relax_table).shape[0] > 1
@@ -451,8 +451,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--workload", default="abdominal_2d")
     ap.add_argument("--n3d", type=int, default=1024, help="cube side of the skull_3d workload")
-    ap.add_argument("--relax", type=int, default=4,
-                    help="relaxation mechanisms of the abdominal_2d workload (1..8 where fits exist)")
+    ap.add_argument("--relax", type=int, default=None,
+                    help="relaxation mechanisms (abdominal_2d: 3..8, default 4; skull_3d: 2 or 5..8, default 2)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true", help="skip the batched-serving leg")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint (gradient) leg")

@@ -202,6 +202,16 @@ def test_skull_3d_small_cube():
     compare(f, tr, ref, rtr, "skull_3d_96", prob=prob)
 
 
+def test_skull_3d_small_cube_eight_mechanisms():
+    """The transcranial recipe with the fitted 8-mechanism tuples on a 64^3
+    cube with 10-cell layers."""
+    prob = W.skull_3d(n=64, nb=10, ntr=6, n_steps=160, L=8)
+    _say("skull_3d 64^3 L=8 160 steps")
+    f, tr, _ = gpu_run(prob, prob.n_steps)
+    ref, rtr = oracle_run(prob, prob.n_steps)
+    compare(f, tr, ref, rtr, "skull_3d_64_L8", prob=prob)
+
+
 def test_skull_3d_full_size_window():
     """The 1024^3 grid of the transcranial workload in the benchmark's launch
     configuration (plane-prefetch sweeps over 64 x 8 columns, 64 planes per

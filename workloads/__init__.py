@@ -300,7 +300,7 @@ def abdominal_2d(nx=4096, ny=2048, seed=2, n_steps=12000, ppw=12, f0=3e6, cfl=0.
 # Workload 3: 3D transcranial-like medium, L = 2
 # ---------------------------------------------------------------------------
 
-def skull_3d(n=1024, nb=48, ntr=36, seed=3, n_steps=4000, ppw=12, f0=1e6, cfl=0.4, n_rcv=1024):
+def skull_3d(n=1024, nb=48, ntr=36, seed=3, n_steps=4000, ppw=12, f0=1e6, cfl=0.4, n_rcv=1024, L=2):
     """Cube of n^3 points including nb-cell layers: brain-like background
     (c 1540, rho 1040, beta 4; Table 2 tuple), a curved bone-like shell
     (thickness 4-8 cells = 0.5-1 mm at 12 ppw / 1 MHz; c 2800, rho 1900,
@@ -309,7 +309,11 @@ def skull_3d(n=1024, nb=48, ntr=36, seed=3, n_steps=4000, ppw=12, f0=1e6, cfl=0.
     domain, radius of curvature equal to it, apex 8 cells below the top
     layer) and its focus; receivers on the focal axis.  The geometry scales
     with n (same recipe on smaller cubes for parity tests).  z is the depth
-    (slowest) axis."""
+    (slowest) axis.  With L = 5..8 the two tissues take the fitted 5..8
+    mechanism tuples of 0.5 dB/MHz/cm (background) and 1.5 dB/MHz^1.3/cm
+    (shell), the only laws fitted with that many mechanisms."""
+    if L != 2 and not 5 <= L <= 8:
+        raise ValueError("skull_3d takes L = 2 or 5..8")
     rng = np.random.default_rng(seed)
     h = grid_spacing(1540.0, f0, ppw)
     Ldom = n * h
@@ -352,11 +356,14 @@ def skull_3d(n=1024, nb=48, ntr=36, seed=3, n_steps=4000, ppw=12, f0=1e6, cfl=0.
         rho[z][m] = (1900.0 * (1.0 + 0.1 * noise)).astype(np.float32)
         label[z][m] = 1
     dt = cfl * h / float(c.max())
-    rows = [TABLE2_ROW, tissue_row(8.0, 1.0, 2, 1e6)]
-    prob = Problem(shape=(n, n, n), h=h, dt=dt, n_relax=2, c=c, rho=rho, beta=beta,
+    if L == 2:
+        rows = [TABLE2_ROW, tissue_row(8.0, 1.0, 2, 1e6)]
+    else:
+        rows = [tissue_row(0.5, 1.0, L, 3e6), tissue_row(1.5, 1.3, L, 3e6)]
+    prob = Problem(shape=(n, n, n), h=h, dt=dt, n_relax=L, c=c, rho=rho, beta=beta,
                    relax_table=np.asarray(rows, np.float64), label=label,
                    bound_cells=(nb,) * 3, trans_cells=(ntr,) * 3, n_steps=n_steps,
-                   name="skull_3d_%d" % n)
+                   name="skull_3d_%d" % n + ("" if L == 2 else "_L%d" % L))
     # focused spherical cap: voxels within half a cell of the sphere of radius
     # Rcurv about the focus, inside the aperture, above the focus
     zs = np.arange(apex, int(np.ceil(zf)))
