@@ -10,6 +10,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <thread>
 #include <utility>
 #include <vector>
 
@@ -435,29 +436,61 @@ fw2_status fw2_create_domain(const fw2_domain_desc *desc, void *dev_workspace, u
     }
 
     // Medium planes: kappa0 = 1/(rho c^2), kappa0 (1 - 2 beta), rho (FP64, stored FP32).
+    // Planes are converted in chunks of about 16 M points by up to 16 host
+    // threads (a share of the chunk's rows each) and each chunk is uploaded
+    // with one copy per array: the planes of a chunk are contiguous on the
+    // device.  Halo cells of the staging buffers are never written and stay
+    // zero.
     {
         const size_t plane_n = (size_t)g.plane;
-        std::vector<float> hk(plane_n, 0.f), hn(plane_n, 0.f), hr(plane_n, 0.f);
-        std::vector<uint8_t> hl(a.label ? plane_n : 0, 0);
+        const int nz = g.n[2];
+        const int cz = (int)std::max<size_t>(1, std::min<size_t>((size_t)nz, ((size_t)1 << 24) / plane_n));
+        const size_t chunk_n = plane_n * (size_t)cz;
+        std::vector<float> hk(chunk_n, 0.f), hn(chunk_n, 0.f), hr(chunk_n, 0.f);
+        std::vector<uint8_t> hl(a.label ? chunk_n : 0, 0);
         const int64_t z0 = nd == 3 ? fw2::kHalo : 0;
-        for (int z = 0; z < g.n[2]; ++z) {
-            for (int y = 0; y < g.n[1]; ++y)
-                for (int x = 0; x < g.n[0]; ++x) {
-                    const int64_t q = ((int64_t)z * g.n[1] + y) * g.n[0] + x;
-                    const size_t o = (size_t)(y + fw2::kHalo) * g.pitch + x + fw2::kHalo;
-                    const double c = desc->c[q], rr = desc->rho[q], b = desc->beta[q];
-                    const double k0 = 1.0 / (rr * c * c);
-                    hk[o] = (float)k0;
-                    hn[o] = (float)(k0 * (1.0 - 2.0 * b));
-                    hr[o] = (float)rr;
-                    if (a.label) hl[o] = desc->label[q];
+        const unsigned hw = std::thread::hardware_concurrency();
+        const int n_thr = (int)std::max(1u, std::min(16u, hw ? hw : 1u));
+        for (int zc = 0; zc < nz; zc += cz) {
+            const int nzc = std::min(cz, nz - zc);
+            const int64_t rows = (int64_t)nzc * g.n[1];
+            auto convert = [&](int64_t r0, int64_t r1) {
+                for (int64_t r = r0; r < r1; ++r) {
+                    const int zl = (int)(r / g.n[1]), y = (int)(r % g.n[1]);
+                    const int64_t q0 = ((int64_t)(zc + zl) * g.n[1] + y) * g.n[0];
+                    const size_t o0 = (size_t)zl * plane_n + (size_t)(y + fw2::kHalo) * g.pitch + fw2::kHalo;
+                    for (int x = 0; x < g.n[0]; ++x) {
+                        const int64_t q = q0 + x;
+                        const size_t o = o0 + x;
+                        const double c = desc->c[q], rr = desc->rho[q], b = desc->beta[q];
+                        const double k0 = 1.0 / (rr * c * c);
+                        hk[o] = (float)k0;
+                        hn[o] = (float)(k0 * (1.0 - 2.0 * b));
+                        hr[o] = (float)rr;
+                        if (a.label) hl[o] = desc->label[q];
+                    }
                 }
-            const int64_t off = (z + z0) * g.plane;
-            FW2_HIP_C(hipMemcpy(kap + off, hk.data(), plane_n * 4, hipMemcpyHostToDevice));
-            FW2_HIP_C(hipMemcpy(nlq + off, hn.data(), plane_n * 4, hipMemcpyHostToDevice));
-            FW2_HIP_C(hipMemcpy(rho + off, hr.data(), plane_n * 4, hipMemcpyHostToDevice));
+            };
+            const int nt = (int)std::min<int64_t>(n_thr, std::max<int64_t>(1, rows / 64));
+            // ranges whose thread could not be started run on this thread
+            std::vector<std::thread> pool;
+            int started = 0;
+            try {
+                pool.reserve(nt);
+                for (int t = 1; t < nt; ++t, ++started)
+                    pool.emplace_back(convert, rows * t / nt, rows * (t + 1) / nt);
+            } catch (...) {
+            }
+            convert(0, rows / nt);
+            for (int t = 1 + started; t < nt; ++t) convert(rows * t / nt, rows * (t + 1) / nt);
+            for (auto &th : pool) th.join();
+            const int64_t off = (zc + z0) * g.plane;
+            const size_t n = plane_n * (size_t)nzc;
+            FW2_HIP_C(hipMemcpy(kap + off, hk.data(), n * 4, hipMemcpyHostToDevice));
+            FW2_HIP_C(hipMemcpy(nlq + off, hn.data(), n * 4, hipMemcpyHostToDevice));
+            FW2_HIP_C(hipMemcpy(rho + off, hr.data(), n * 4, hipMemcpyHostToDevice));
             if (a.label)
-                FW2_HIP_C(hipMemcpy((uint8_t *)a.label + off, hl.data(), plane_n, hipMemcpyHostToDevice));
+                FW2_HIP_C(hipMemcpy((uint8_t *)a.label + off, hl.data(), n, hipMemcpyHostToDevice));
         }
     }
 
