@@ -156,6 +156,20 @@ def test_heterogeneous_2d_eight_mechanisms():
     compare(f, tr, ref, rtr, "abdominal_2d_full_L8", prob=prob)
 
 
+def test_medium_upload_in_chunks_with_a_partial_last_chunk():
+    """A long 3D grid (24 x 24 x 9000) whose medium is uploaded in two chunks
+    of planes (8192 and 808 planes of 64 x 32 padded points), the last one
+    partial; c, rho, beta and the label differ at every point, so a plane
+    placed at the wrong depth changes the fields.  A seeded random state over
+    the whole grid advanced 2 steps matches the oracle everywhere."""
+    prob = W.random_medium((24, 24, 9000), 1, 3, seed=77, nb=6, ntr=2)
+    st = _state(prob, 23)
+    _say("random_medium 24x24x9000 L=1 random state, 2 steps")
+    f, tr, _ = gpu_run(prob, 2, state=st)
+    ref, rtr = oracle_run(prob, 2, state=st)
+    compare(f, tr, ref, rtr, "chunked_upload_3d", prob=prob)
+
+
 # -------------------------------------------------------- random states ---
 
 @pytest.mark.parametrize("shape,L,scheme,labels", [
