@@ -152,21 +152,35 @@ def probe_copy(torch, dev, mib, reps=10):
 
 
 def serving_leg(seed=4):
-    """Continuous batching vs the plain one-at-a-time solver on three seeded
+    """Continuous batching vs the plain one-at-a-time solver on four seeded
     request streams of the heterogeneous 2D recipe: 8 requests at the served
-    workload's own sizes and step counts (1024^2-3072^2), 48 at 512^2-1024^2
-    and 96 small 128^2-384^2 grids.  Capacity: all requests queued at t = 0.
-    Latency: Poisson arrivals at 1.2x the plain solver's capacity."""
+    workload's own sizes and step counts (1024^2-3072^2), 48 at 512^2-1024^2,
+    96 small 128^2-384^2 grids, and 48 small grids mixing every launch class
+    (3, 4 or 8 mechanisms; every third request with per-point stencil
+    weights).  Capacity: all requests queued at t = 0.  Latency: Poisson
+    arrivals at 1.2x the plain solver's capacity."""
     import workloads as W
-    from paper_2106_11476_amd import serve
+    from paper_2106_11476_amd import fw2, serve
     out = {}
-    for name, (n, sides, step) in (("workload_1024_3072", (8, (1024, 3072), 256)),
-                                   ("heterogeneous_512_1024", (48, (512, 1024), 128)),
-                                   ("small_128_384", (96, (128, 384), 64))):
-        raw = W.serving_requests(n=n, seed=seed, sides=sides, side_step=step)
+    for name, (n, sides, step, L_choices, local_every) in (
+            ("workload_1024_3072", (8, (1024, 3072), 256, (2, 3, 4), 0)),
+            ("heterogeneous_512_1024", (48, (512, 1024), 128, (2, 3, 4), 0)),
+            ("small_128_384", (96, (128, 384), 64, (2, 3, 4), 0)),
+            ("mixed_classes_128_384", (48, (128, 384), 64, (3, 4, 8), 3))):
+        raw = W.serving_requests(n=n, seed=seed, sides=sides, side_step=step, L_choices=L_choices)
+        if local_every:
+            for i, (p, _, _) in enumerate(raw):
+                if i % local_every == local_every - 1:
+                    p.stencil_mode = fw2.STENCIL_LOCAL
         upd = sum(p.npts * k for p, k, _ in raw)
         mk = lambda arr: [serve.Request(i, p, k, a) for i, ((p, k, _), a) in enumerate(zip(raw, arr))]
-        tile, _ = serve.autotune_tile([p for p, _, _ in raw[:4]], steps=32)
+        # the tuning set holds a domain with more than four mechanisms when
+        # the stream does, so that the tile chosen can run every request
+        tune = [p for p, _, _ in raw[:4]]
+        many = [p for p, _, _ in raw if p.n_relax > 4]
+        if many and all(p.n_relax <= 4 for p in tune):
+            tune.append(many[0])
+        tile, _ = serve.autotune_tile(tune, steps=32)
         med = float(np.median([serve.footprint_bytes(p, k) for p, k, _ in raw]))
         budget = int(24 * med)
         p0 = serve.run_plain(mk([0.0] * n))
@@ -178,7 +192,8 @@ def serving_leg(seed=4):
         bt = srv.run(mk(arr))
         srv.close()
         out[name] = {
-            "requests": n, "sides": list(sides), "tile": list(tile), "budget_bytes": budget,
+            "requests": n, "sides": list(sides), "relax_mechanisms": list(L_choices),
+            "per_point_weights_every": local_every, "tile": list(tile), "budget_bytes": budget,
             "capacity_sims_per_s": {"plain": round(p0.completed / p0.makespan, 3),
                                     "batched": round(b0.completed / b0.makespan, 3)},
             "capacity_gpoint_updates_per_s": {"plain": round(upd / p0.makespan / 1e9, 3),
