@@ -12,7 +12,9 @@
  *     along a.  The v_a sample past the last pressure sample along a lies
  *     outside the grid and is held at zero.  Fields outside the grid are zero.
  *   - All device arithmetic is FP32; derived coefficients are computed in FP64
- *     on the host during fw2_create_domain.
+ *     during fw2_create_domain (on the host, or on the GPU for device maps).
+ *   - A slab domain (slab_nz > 0) is the exception to "zero outside the grid"
+ *     along z: its z halos hold the neighbouring slabs' planes.
  *   - Every call returns fw2_status; nothing throws across the ABI.  On error
  *     fw2_last_error() returns a message for the calling thread.
  *   - A domain is not thread-safe; distinct domains may be used from
@@ -68,6 +70,18 @@ enum { FW2_HOST = 0, FW2_DEVICE = 1 };
  *     fifth of the attenuation at 12 points per wavelength, CFL 0.4. */
 enum { FW2_RELAX_PRINTED = 0, FW2_RELAX_CENTRED = 1 };
 
+/* Nonlinear terms (Sec. 2.2, Eqs. state1 and state2): the momentum update
+ * divides by rho0 (1 + A kappa0 p), the mass update by kappa0 (1 + kappa0 B p).
+ *   FW2_NL_PRINTED: A = 1, B = 1 - 2 beta, the equations of state as printed
+ *     (the default of a zero-initialised descriptor).  Their plane-wave
+ *     coefficient of nonlinearity is beta - 1 (a simple wave of the printed
+ *     system travels at 1/sqrt(rho(p) kappa(p))).
+ *   FW2_NL_CUSTOM: A = nl_A, B = nl_B0 + nl_B1 beta.  A = 0, B = -2 beta gives
+ *     the plane-wave coefficient beta, that of the Westervelt equation to
+ *     which Sec. 2.2 reduces the system once the locally nonlinear terms are
+ *     dropped. */
+enum { FW2_NL_PRINTED = 0, FW2_NL_CUSTOM = 1 };
+
 /* Stencil weights (Sec. 3.1: the (8,4) operator of a time-space design whose
  * weights depend on the Courant number r = c dt / h).
  *   FW2_STENCIL_GLOBAL: one set for the grid, at r = fd_r (or max(c) dt / h).
@@ -84,7 +98,9 @@ typedef struct {
     int32_t ndim;             /* 2 or 3 */
     int32_t n_relax;          /* L, 1..FW2_MAX_RELAX */
     int64_t n[3];             /* nx, ny, nz including the boundary layers; nz = 1 in 2D;
-                                 each 1..2^20, and in 3D (nx + 72)(ny + 8) < 2^29 */
+                                 each 1..2^20; a padded plane must stay addressable with
+                                 32-bit byte offsets: (nx + 72)(ny + 8) < 2^30 in 2D and
+                                 < 2^29 in 3D (FW2_E_INVALID otherwise) */
     double h;                 /* grid step (m) */
     double dt;                /* time step (s) */
     int32_t bound_cells[3];   /* L_C-PML per side per axis, in cells (Sec. 3.3) */
@@ -95,14 +111,22 @@ typedef struct {
     double fd_r;              /* Courant number of the (8,4) weights; <= 0: max(c) dt / h */
     int32_t relax_scheme;     /* FW2_RELAX_PRINTED or FW2_RELAX_CENTRED */
     int32_t stencil_mode;     /* FW2_STENCIL_GLOBAL or FW2_STENCIL_LOCAL */
-    const float *c;           /* host [nz][ny][nx] sound speed (m/s), > 0 */
-    const float *rho;         /* host [nz][ny][nx] equilibrium density rho_0 (kg/m^3), > 0 */
-    const float *beta;        /* host [nz][ny][nx] coefficient of nonlinearity 1 + B/2A */
-    const uint8_t *label;     /* host [nz][ny][nx] relaxation-tuple index, or NULL (all 0) */
+    const float *c;           /* [nz][ny][nx] sound speed (m/s), > 0 (host or device: map_kind) */
+    const float *rho;         /* [nz][ny][nx] equilibrium density rho_0 (kg/m^3), > 0 */
+    const float *beta;        /* [nz][ny][nx] coefficient of nonlinearity 1 + B/2A */
+    const uint8_t *label;     /* [nz][ny][nx] relaxation-tuple index, or NULL (all 0) */
     int32_t n_labels;         /* rows of relax_table, 1..FW2_MAX_LABELS */
     const double *relax_table;/* host [n_labels][2 + 4L]: k1, k2, d1[L], d2[L], alpha1[L],
                                  alpha2[L] -- the 2 + 4L isotropic parameters of Sec. 3.2 */
     void *stream;             /* hipStream_t for all work of the domain; NULL = null stream */
+    int32_t nonlinear_form;   /* FW2_NL_PRINTED (0) or FW2_NL_CUSTOM */
+    double nl_A, nl_B0, nl_B1;/* FW2_NL_CUSTOM coefficients (finite); ignored otherwise */
+    int32_t map_kind;         /* FW2_HOST (0): c, rho, beta, label are host arrays;
+                                 FW2_DEVICE: device arrays, converted on the GPU (same
+                                 FP64 arithmetic, bitwise the same domain) */
+    int64_t slab_z0;          /* slab_nz > 0: this domain is planes [slab_z0, slab_z0 + nz)   */
+    int64_t slab_nz;          /*   of a 3D grid of slab_nz planes (see the slab calls below); */
+                              /*   0: the domain is the whole grid                           */
 } fw2_domain_desc;
 
 /* Bytes of device workspace a domain described by desc needs (host-only
@@ -132,7 +156,9 @@ fw2_status fw2_add_source(fw2_domain *dom, int32_t n_pts, const int64_t *flat_id
                           const int32_t *sig_id, const float *weight, int32_t n_sig,
                           int32_t n_t, const float *signals);
 
-/* Pressure receivers: after the sources of step k, trace[k][r] = p[flat_idx[r]]
+/* Pressure receivers (library infrastructure: the paper's experiments record
+ * the pressure at receiving positions, e.g. the echoes of Sec. 5's transmit
+ * events): after the sources of step k, trace[k][r] = p[flat_idx[r]]
  * for k < cap_steps (rows are global step indices).
  *   flat_idx and trace: caller-owned DEVICE arrays, trace is [cap_steps][n_rcv]
  *   FP32.  A call replaces the previous receiver set; n_rcv = 0 removes it. */
@@ -146,32 +172,38 @@ fw2_status fw2_add_receivers(fw2_domain *dom, int32_t n_rcv, const int64_t *flat
 fw2_status fw2_step(fw2_domain *dom, int32_t n);
 
 /* Copy the selected fields (order of the FW2_FIELD_ enum) into dst, packed,
- * unpadded FP32.  dst_kind FW2_HOST or FW2_DEVICE.  Synchronises the stream. */
+ * unpadded FP32 (the state of Sec. 3.1's scheme: p, v and the memory variables
+ * of Sec. 3.2).  dst_kind FW2_HOST or FW2_DEVICE.  Synchronises the stream.
+ * FW2_E_STATE for a NULL domain, FW2_E_INVALID for a bad mask, kind or NULL
+ * dst. */
 fw2_status fw2_read_fields(fw2_domain *dom, uint32_t field_mask, void *dst, int32_t dst_kind);
 
-/* Overwrite the selected fields from src (same packing); for checkpoint and
- * resume.  Values at v samples outside the grid are ignored (kept zero).
- * Synchronises the stream. */
+/* Overwrite the selected fields from src (same packing; library
+ * infrastructure for checkpoint and resume of Sec. 3.1's state).  Values at v
+ * samples outside the grid are ignored (kept zero).  Synchronises the stream.
+ * Errors as fw2_read_fields. */
 fw2_status fw2_write_fields(fw2_domain *dom, uint32_t field_mask, const void *src, int32_t src_kind);
 
-/* Global index of the next step (sources and receivers use it). */
+/* Library infrastructure.  Global index of the next step (sources and
+ * receivers use it); -1 for a NULL domain. */
 int64_t fw2_current_step(const fw2_domain *dom);
 
-/* Set the global step index (resume from a checkpoint).  Synchronises. */
+/* Library infrastructure.  Set the global step index (resume from a
+ * checkpoint).  Synchronises.  FW2_E_INVALID for step < 0. */
 fw2_status fw2_set_current_step(fw2_domain *dom, int64_t step);
 
-/* Move the domain to another stream: finishes the work queued on its current
+/* Library infrastructure.  Move the domain to another stream: finishes the work queued on its current
  * stream, then queues every later call of this domain (steps, transfers,
  * checkpoints, the adjoint) on stream (NULL: the default stream).  The caller
  * keeps the stream alive while the domain uses it.  A domain can be built on
  * a setup stream while other work runs, then stepped on a serving stream. */
 fw2_status fw2_set_stream(fw2_domain *dom, void *stream);
 
-/* Steps captured per HIP graph replay (0 disables graphs; default 32).
+/* Library infrastructure.  Steps captured per HIP graph replay (0 disables graphs; default 32).
  * Graph and direct launches give bitwise identical results. */
 fw2_status fw2_set_graph_chunk(fw2_domain *dom, int32_t steps);
 
-/* Per-kernel HIP-event timing on the domain's stream.  While enabled, steps
+/* Library infrastructure (measurement).  Per-kernel HIP-event timing on the domain's stream.  While enabled, steps
  * are launched directly (no graphs) with events around the pressure and
  * velocity kernels.  fw2_get_kernel_timing synchronises and returns the total
  * milliseconds and launch counts since timing was enabled:
@@ -179,8 +211,9 @@ fw2_status fw2_set_graph_chunk(fw2_domain *dom, int32_t steps);
 fw2_status fw2_enable_kernel_timing(fw2_domain *dom, int32_t enable);
 fw2_status fw2_get_kernel_timing(fw2_domain *dom, double ms[2], int64_t count[2]);
 
-/* Watchdog: synchronises and checks that every pressure sample is finite and
- * below limit in magnitude; FW2_E_UNSTABLE otherwise. */
+/* Library infrastructure (watchdog): synchronises and checks that every
+ * pressure sample is finite and below limit in magnitude; FW2_E_UNSTABLE
+ * otherwise. */
 fw2_status fw2_check_finite(fw2_domain *dom, float limit);
 
 /* ---- State blocks and the discrete adjoint ------------------------------
@@ -251,10 +284,63 @@ fw2_status fw2_batch_step(fw2_batch *b, int32_t n);
 fw2_status fw2_batch_set_tile(fw2_batch *b, int32_t cols, int32_t rows);
 void fw2_batch_destroy(fw2_batch *b);
 
-/* Message of the last failed call on this thread ("" if none). */
+/* ---- Relaxation maps to labels -------------------------------------------
+ * Sec. 3.2 gives every point its own 2 + 4L relaxation parameters; the library
+ * stores a label per point and a table of the distinct tuples.  This call
+ * turns dense per-point maps into that form.
+ *   maps: host FP64 [2 + 4L][n_pts] -- one map per parameter, in the
+ *     relax_table row order (k1, k2, d1[L], d2[L], alpha1[L], alpha2[L]), each
+ *     [nz][ny][nx].
+ *   label: host [n_pts] output; table: host [FW2_MAX_LABELS][2 + 4L] output
+ *     (distinct tuples in order of first appearance, compared bitwise);
+ *     *n_labels: their count.
+ * FW2_E_INVALID for NULL pointers, n_pts < 1, a bad n_relax, or more than
+ * FW2_MAX_LABELS distinct tuples (then label and table are unspecified). */
+fw2_status fw2_label_relaxation_map(int64_t n_pts, int32_t n_relax, const double *maps, uint8_t *label,
+                                    double *table, int32_t *n_labels);
+
+/* ---- Slabs of a 3D grid ----------------------------------------------------
+ * The finite-difference update is local (Sec. 5.3 remarks that this suits
+ * several GPUs): a 3D grid split along z into slabs advances each slab with
+ * the same kernels once its z halos hold the neighbours' planes.  A slab
+ * domain (slab_nz > 0, ndim 3, nz >= 4, fd_r > 0 and pml_cp > 0 so that every
+ * slab uses the same stencil and layer constants) follows the global plane
+ * index for the boundary layer and the last v_z sample; its maps, sources and
+ * receivers are its own planes only.  Halo kinds:
+ *   FW2_HALO_P       4 planes of p (exchange after the pressure phase);
+ *   FW2_HALO_V       4 planes of v_z and 1 plane each of v_x and v_y (the g_11
+ *                    cross terms), after the velocity phase;
+ *   FW2_HALO_MEDIUM  1 plane of rho and of kappa0 (the staggered means at the
+ *                    last plane), once after creation.
+ * The memory variables are point-local and never exchanged.  With neighbours
+ * A (below) and B (above), one exchange is pack(A, HIGH) -> unpack(B, LOW) and
+ * pack(B, LOW) -> unpack(A, HIGH); a side without a neighbour keeps its zero
+ * halo.  On several GPUs the packed faces travel between the pack and the
+ * unpack (e.g. over RCCL); on one GPU they are plain device buffers.
+ *   fw2_halo_bytes: bytes of one packed face of the kind.
+ *   fw2_halo_pack: the planes the neighbour on `side` needs, unpadded FP32
+ *     [planes][ny][nx], into the caller's device buffer (async on the
+ *     domain's stream).
+ *   fw2_halo_unpack: a neighbour's packed face into this domain's halo on
+ *     `side` (async on the domain's stream).
+ *   fw2_step_phase: half a step, FW2_PHASE_PRESSURE (pressure phase and
+ *     sources) or FW2_PHASE_VELOCITY (receivers and velocity phase; the step
+ *     counter then advances); the phases must alternate (FW2_E_STATE), and
+ *     fw2_step is refused between them.
+ * Errors: FW2_E_INVALID for a bad kind, side or phase or a NULL buffer,
+ * FW2_E_UNSUPPORTED for halo calls on a domain that is not a slab. */
+enum { FW2_HALO_P = 0, FW2_HALO_V = 1, FW2_HALO_MEDIUM = 2 };
+enum { FW2_LOW = 0, FW2_HIGH = 1 };
+enum { FW2_PHASE_PRESSURE = 0, FW2_PHASE_VELOCITY = 1 };
+fw2_status fw2_halo_bytes(const fw2_domain *dom, int32_t kind, uint64_t *bytes);
+fw2_status fw2_halo_pack(fw2_domain *dom, int32_t kind, int32_t side, void *dev_dst);
+fw2_status fw2_halo_unpack(fw2_domain *dom, int32_t kind, int32_t side, const void *dev_src);
+fw2_status fw2_step_phase(fw2_domain *dom, int32_t phase);
+
+/* Library infrastructure.  Message of the last failed call on this thread ("" if none). */
 const char *fw2_last_error(void);
 
-/* Free host-side state (events, graphs).  Does not touch the workspace,
+/* Library infrastructure.  Free host-side state (events, graphs).  Does not touch the workspace,
  * sources or traces, which the caller owns.  NULL is a no-op. */
 void fw2_destroy_domain(fw2_domain *dom);
 

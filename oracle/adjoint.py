@@ -1,19 +1,20 @@
 """FP64 discrete adjoint of the oracle's time stepper (test infrastructure).
 
-The paper notes (Sec. 5, extension to full waveform inversion) that the
-relaxation mechanisms are not time-reversible, so the adjoint of the relaxing
-operators has to be derived explicitly rather than obtained by running the
-forward scheme backwards.  This module is that derivation for the discrete
+Sec. 5 (extension to full waveform inversion): the memory-variable
+recursion dissipates, so a gradient cannot come from stepping the forward
+scheme backwards in time.  This module transposes the linearised discrete
 scheme of oracle.solver (memory scheme 1, time-centred), in reverse-mode
 form, for the misfit J = 1/2 sum_n sum_r (trace[n][r] - obs[n][r])^2.
 
 Forward step n (input state p, v, m1 = psi1, m2 = psi2; x = kappa0):
   pressure:  D_a = (D^- v_a);  S = sum_a (w2_a D_a + sum_nu m2_a,nu)
-             m2' = b2 m2 + c2 D;  K = x (1 + x (1 - 2 beta) p);  p' = p - dt S / K
+             m2' = b2 m2 + c2 D;  K = x (1 + nlq p), nlq = x B (B = 1 - 2 beta
+             as printed);  p' = p - dt S / K
   sources:   p'' = p' + s_n
   receivers: trace_n = p''[R]
   velocity:  D' = (D^+ p'')_a;  S' = w1 D' + sum_nu m1;  m1' = b1 m1 + c1 D'
-             Q = rho_a (1 + x_a pbar), x_a and pbar the means of the two cells
+             Q = rho_a (1 + A x_a pbar), x_a and pbar the means of the two cells
+             (A = 1 as printed)
              v' = v - dt S' / Q     (only for v samples inside the grid)
 with w = 1/kappa + sum_nu e0, c = e1 + b e0 (oracle.relaxation.centred_weights).
 The adjoint uses (D^-)^T = -(D^+) and (D^+)^T = -(D^-) (zero outside the grid,
@@ -127,7 +128,7 @@ def forward_step(prob, maps, st, step):
         D = d_plus(pp, a, maps)
         Sv = w1[a] * D + st.psi1[a].sum(axis=0)
         pbar = 0.5 * (pp + _sh(pp, nd, grid, _e(a, 1)))
-        Q = maps.rho_v[a] * (1.0 + maps.kap_v[a] * pbar)
+        Q = maps.rho_v[a] * (1.0 + maps.nl_A * maps.kap_v[a] * pbar)
         vn[a] = np.where(ins, st.v[a] - maps.dt * Sv / Q, st.v[a])
         for nu in range(L):
             m1n[a, nu] = np.where(ins, b1[a, nu] * st.psi1[a, nu] + c1[a, nu] * D, st.psi1[a, nu])
@@ -158,12 +159,12 @@ def reverse_step(prob, maps, st, lam, residual, gk):
         Sv = w1[a] * D + st.psi1[a].sum(axis=0)
         pnext = _sh(pp, nd, grid, _e(a, 1))
         pbar = 0.5 * (pp + pnext)
-        Q = maps.rho_v[a] * (1.0 + maps.kap_v[a] * pbar)
+        Q = maps.rho_v[a] * (1.0 + maps.nl_A * maps.kap_v[a] * pbar)
         lv = np.where(ins, lam.v[a], 0.0)
         lS = -dt * lv / Q
         lQ = dt * Sv * lv / (Q * Q)
-        lpbar = lQ * maps.rho_v[a] * maps.kap_v[a]
-        lk = lQ * maps.rho_v[a] * pbar
+        lpbar = lQ * maps.rho_v[a] * maps.nl_A * maps.kap_v[a]
+        lk = lQ * maps.rho_v[a] * maps.nl_A * pbar
         lD = w1[a] * lS
         for nu in range(L):
             lm1n = np.where(ins, lam.psi1[a, nu], 0.0)

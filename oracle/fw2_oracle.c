@@ -20,7 +20,8 @@
  *          scheme 1 (time-centred convolution, D linear between samples):
  *            M = e0 D_a + psi2 ;  psi2 <- b2 psi2 + (a2 - e0 + b2 e0) D_a
  *        S      = sum_a ( ik2 D_a + sum_nu M )    Eq. relaxation4 (nabla_2)
- *        p     <- p - dt S / (kappa0 (1 + kappa0 (1 - 2 beta) p))   Eq. general6
+ *        p     <- p - dt S / (kappa0 (1 + kappa0 B p))   Eq. general6,
+ *                 B = 1 - 2 beta as printed (Eq. state2)
  *   2. sources:   p[idx] += w * signal[step]
  *   3. receivers: trace[step][r] = p[idx_r]
  *   4. velocity phase, every v_a point (half-integer position along a)
@@ -29,8 +30,9 @@
  *        D      = (D^+ p)_a
  *        memory terms as in step 1 with (a1, b1, e0_1)
  *        S      = ik1 D + sum_nu M                     (nabla_1)
- *        v_a   <- v_a - dt S / (rho_a (1 + kappa0_a pbar)),  pbar = mean of the
- *                 two pressures around the v point      Eq. general5
+ *        v_a   <- v_a - dt S / (rho_a (1 + A kappa0_a pbar)),  pbar = mean of
+ *                 the two pressures around the v point, A = 1 as printed
+ *                 (Eq. state1)                          Eq. general5
  */
 #include <stdint.h>
 #include <stddef.h>
@@ -48,7 +50,7 @@ typedef struct {
     double g[4];             /* g_m0 / h, m = 1..4 */
     double g11;              /* g_11 / h */
     const double *kap0;      /* [npts] equilibrium compressibility at p points */
-    const double *nlq;       /* [npts] kappa0 (1 - 2 beta) at p points */
+    const double *nlq;       /* [npts] kappa0 B at p points (B = 1 - 2 beta as printed) */
     const double *rho_v;     /* [ndim][npts] density at v_a points */
     const double *kap_v;     /* [ndim][npts] compressibility at v_a points */
     const double *ik1;       /* [ndim][npts] 1/kappa_1 at v_a points */
@@ -69,6 +71,9 @@ typedef struct {
      * g_10 .. g_40, g_11, all over h. */
     const double *gw_p;
     const double *gw_v;
+    /* Coefficient A of the momentum multiplier rho_a (1 + A kappa0_a pbar)
+     * (Eq. state1: A = 1); the mass multiplier's B is folded into nlq. */
+    double nl_A;
 } oracle_problem;
 
 /* Field value at integer coordinate x (x[0] fastest); zero outside the grid. */
@@ -200,7 +205,7 @@ static void velocity_phase(const oracle_problem *P, const double *p, double *v, 
                 }
                 const double S = P->ik1[a * npts + idx] * D + acc;
                 const double pbar = 0.5 * (at(p, P->n, x) + at_shift(p, P->n, x, a, 1, -1, 0));
-                const double rho = P->rho_v[a * npts + idx] * (1.0 + P->kap_v[a * npts + idx] * pbar);
+                const double rho = P->rho_v[a * npts + idx] * (1.0 + P->nl_A * P->kap_v[a * npts + idx] * pbar);
                 v[a * npts + idx] -= P->dt * S / rho;
             }
         }

@@ -46,13 +46,17 @@ def greens_3d_freq(omega, r, c):
     return np.exp(-1j * np.asarray(omega) * r / c) / (4.0 * np.pi * c * c * r)
 
 
-def simple_wave_speed(p, rho0, kappa0, beta):
+def simple_wave_speed(p, rho0, kappa0, beta, nl=(1.0, 1.0, -2.0)):
     """Local propagation speed 1/sqrt(rho(p) kappa(p)) of the 1D lossless
-    system with the equation of state of Eqs. state1 / state2."""
-    return 1.0 / np.sqrt(rho0 * (1.0 + kappa0 * p) * kappa0 * (1.0 + kappa0 * (1.0 - 2.0 * beta) * p))
+    system with rho = rho0 (1 + A kappa0 p), kappa = kappa0 (1 + kappa0 B p),
+    B = B0 + B1 beta; nl = (A, B0, B1), as printed in Eqs. state1 / state2
+    (1, 1, -2) by default."""
+    A, B0, B1 = nl
+    B = B0 + B1 * beta
+    return 1.0 / np.sqrt(rho0 * (1.0 + A * kappa0 * p) * kappa0 * (1.0 + kappa0 * B * p))
 
 
-def simple_wave_propagate(t, f_samples, dist, rho0, kappa0, beta):
+def simple_wave_propagate(t, f_samples, dist, rho0, kappa0, beta, nl=(1.0, 1.0, -2.0)):
     """Pre-shock solution p(x0 + dist, t) of a right-going simple wave whose
     waveform at x0 is f (sampled on the uniform grid t).
 
@@ -62,7 +66,7 @@ def simple_wave_propagate(t, f_samples, dist, rho0, kappa0, beta):
     before a shock forms).
     """
     f = np.asarray(f_samples, dtype=np.float64)
-    arrival = np.asarray(t, dtype=np.float64) + dist / simple_wave_speed(f, rho0, kappa0, beta)
+    arrival = np.asarray(t, dtype=np.float64) + dist / simple_wave_speed(f, rho0, kappa0, beta, nl)
     if np.any(np.diff(arrival) <= 0):
         raise ValueError("characteristics cross: shock formed")
     return np.interp(t, arrival, f, left=0.0, right=0.0)

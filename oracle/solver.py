@@ -11,6 +11,9 @@ Test infrastructure only.  Follows the paper's method as written:
   derivative with the directional two-stage profile.
 * Eqs. general5 / general6 with the equation of state of Eqs. state1 /
   state2: rho = rho0 (1 + kappa0 p), kappa = kappa0 (1 + kappa0 (1-2 beta) p).
+  prob.nonlinear_form 1 replaces them by rho0 (1 + A kappa0 p) and
+  kappa0 (1 + kappa0 (B0 + B1 beta) p) (A = 1, B0 = 1, B1 = -2 as printed;
+  A = 0, B0 = 0, B1 = -2 gives a plane-wave nonlinearity coefficient beta).
 * Sec. 3.1: staggered leapfrog with the (8,4) stencil.
 * Memory variables, two schemes (prob.relax_scheme):
   0 -- Eq. relaxation_psi as printed: psi^n = b psi^{n-1} + a D^{n-1/2}, the
@@ -73,6 +76,7 @@ class _Problem(ctypes.Structure):
         ("src_w", ctypes.c_void_p), ("n_t", ctypes.c_int32), ("signals", ctypes.c_void_p),
         ("n_rcv", ctypes.c_int32), ("rcv_idx", ctypes.c_void_p),
         ("gw_p", ctypes.c_void_p), ("gw_v", ctypes.c_void_p),
+        ("nl_A", ctypes.c_double),
     ]
 
 
@@ -125,6 +129,15 @@ class Maps:
     """All per-point FP64 coefficient arrays of one problem."""
 
 
+def nonlinear_coefficients(prob):
+    """(A, B0, B1) of the multipliers rho0 (1 + A kappa0 p) and
+    kappa0 (1 + kappa0 (B0 + B1 beta) p): Eqs. state1 / state2 as printed
+    give (1, 1, -2); prob.nonlinear_form = 1 takes prob.nl_A, nl_B0, nl_B1."""
+    if int(getattr(prob, "nonlinear_form", 0)) == 1:
+        return float(prob.nl_A), float(prob.nl_B0), float(prob.nl_B1)
+    return 1.0, 1.0, -2.0
+
+
 def coefficient_maps(prob):
     """Compute every derived coefficient from the problem's inputs (FP64).
 
@@ -141,10 +154,13 @@ def coefficient_maps(prob):
     m.ndim, m.L, m.grid = ndim, L, grid
     m.dt, m.h = float(prob.dt), float(prob.h)
 
-    # Medium: kappa0 = 1/(rho0 c^2) (compressibility, Sec. 2.2), kappa0 (1-2 beta).
+    # Medium: kappa0 = 1/(rho0 c^2) (compressibility, Sec. 2.2), kappa0 B with
+    # B = 1 - 2 beta as printed (Eq. state2), and the momentum multiplier's A.
     kap0 = 1.0 / (rho * c * c)
     m.kap0 = kap0
-    m.nlq = kap0 * (1.0 - 2.0 * beta)
+    A, B0, B1 = nonlinear_coefficients(prob)
+    m.nl_A = A
+    m.nlq = kap0 * (B0 + B1 * beta)
     m.rho_v = np.stack([0.5 * (rho + _next_along(rho, ndim, a)) for a in range(ndim)])
     m.kap_v = np.stack([0.5 * (kap0 + _next_along(kap0, ndim, a)) for a in range(ndim)])
 
@@ -282,6 +298,7 @@ def run(prob, n_steps, state=None, maps=None, record=True):
     P.rcv_idx = ptr(ridx, np.int64)
     P.gw_p = ptr(maps.gw_p) if maps.gw_p is not None else None
     P.gw_v = ptr(maps.gw_v) if maps.gw_v is not None else None
+    P.nl_A = float(maps.nl_A)
     for name in ("p", "v", "psi1", "psi2"):
         arr = getattr(state, name)
         if not (arr.flags.c_contiguous and arr.dtype == np.float64):
@@ -401,7 +418,7 @@ def numpy_run(prob, n_steps, state=None, maps=None):
                 acc += _memory(maps.scheme, state.psi1, a, nu, maps.a1, maps.b1, maps.e0_1, D)
             Sv = maps.ik1[a] * D + acc
             pbar = 0.5 * (state.p + _shift(pp, ndim, grid, e(a, 1)))
-            vnew = state.v[a] - maps.dt * Sv / (maps.rho_v[a] * (1.0 + maps.kap_v[a] * pbar))
+            vnew = state.v[a] - maps.dt * Sv / (maps.rho_v[a] * (1.0 + maps.nl_A * maps.kap_v[a] * pbar))
             # the sample past the last pressure sample along a is outside
             inside = _along(np.arange(grid[_np_axis(ndim, a)]) < grid[_np_axis(ndim, a)] - 1, ndim, a)
             state.v[a] = np.where(inside, vnew, state.v[a])
@@ -409,3 +426,41 @@ def numpy_run(prob, n_steps, state=None, maps=None):
                 state.psi1[a, nu] = np.where(inside, state.psi1[a, nu], psi1_old[a][nu])
         state.step += 1
     return state, trace
+
+
+def divergence(v, maps):
+    """Sum over the axes of (D^- v_a) at every pressure point (Sec. 3.1
+    stencil, the operator of the pressure phase), FP64.
+
+    v is [ndim] + grid (any float dtype); the weights are the problem's own
+    (global, or per point with stencil_mode 1).  With no memory variables and
+    p = 0 before the step, the pressure phase sets p = -dt S / kappa0 with S
+    this divergence, which is how the function is pinned against the C
+    stepper.  Used to compare the part of a velocity field that drives the
+    pressure."""
+    ndim, grid = maps.ndim, maps.grid
+    v = np.asarray(v, dtype=np.float64)
+    if maps.stencil_mode == 1:
+        wp = [maps.gw_p[k] for k in range(5)]
+    else:
+        wp = list(maps.g) + [maps.g11]
+
+    def e(a, s=1):
+        o = [0, 0, 0]
+        o[a] = s
+        return o
+
+    out = np.zeros(grid)
+    for a in range(ndim):
+        vp = _pad(v[a])
+        for mm in range(1, 5):
+            out += wp[mm - 1] * (_shift(vp, ndim, grid, e(a, mm - 1)) -
+                                 _shift(vp, ndim, grid, e(a, -mm)))
+        for b in range(ndim):
+            if b == a:
+                continue
+            for sg in (-1, 1):
+                o2 = e(a, -1)
+                o2[b] += sg
+                out += wp[4] * (_shift(vp, ndim, grid, e(b, sg)) - _shift(vp, ndim, grid, o2))
+    return out

@@ -1,9 +1,9 @@
 """Gradient of a receiver-trace misfit with respect to the sound-speed map.
 
-The paper's closing section points at full waveform inversion and notes that
-the relaxation mechanisms are not time-reversible, so the adjoint of the
-relaxing operators has to be derived explicitly.  libfw2 carries that
-derivation as hand-written reverse-step kernels (fw2_adjoint_step): the exact
+Sec. 5 names full waveform inversion as the extension of the method; the
+memory-variable recursion dissipates, so the gradient needs the transpose of
+the discrete step rather than a backwards run of it.  libfw2 implements that
+transpose as hand-written reverse-step kernels (fw2_adjoint_step): the exact
 transpose of one step of the time-centred scheme, linearised about the
 forward state at the step's input.  This module drives them from a
 torch.autograd.Function:

@@ -2,23 +2,26 @@
 // memory scheme), for the gradient of J = 1/2 sum (trace - obs)^2 with
 // respect to kappa0 (and through it the sound speed).
 //
-// The relaxation is not time-reversible (Sec. 5: the adjoint of the
-// relaxation operators must be derived explicitly), so the reverse step is
-// the transpose of the forward step's linearisation, taken phase by phase in
+// The memory-variable recursion is dissipative, so running the forward
+// scheme backwards in time does not give its adjoint (Sec. 5, full waveform
+// inversion): the reverse step here is the transpose of the forward step's
+// linearisation, taken phase by phase in
 // reverse order, about the forward state at the step's input:
 //   A0  pressure points: recompute S = sum_a (w2 D^-v_a + sum psi2) and
-//       p'' = p - dt S / K (+ sources, A_src), K = kappa0 (1 + kappa0 (1-2beta) p)
+//       p'' = p - dt S / K (+ sources, A_src), K = kappa0 (1 + kappa0 B p),
+//       kappa0 B = nlq (B = 1 - 2 beta as printed; B does not depend on kappa0)
 //   A1  v points inside the grid: velocity phase reversed, pointwise:
+//       Q = rho_a (1 + A kappa0_a pbar) (A = 1 as printed),
 //       lam_S' = -dt lam_v / Q, lam_Q = dt S' lam_v / Q^2, lam_psi1 <- lam_S' + b1 lam_psi1,
-//       and per axis the adjoint of D^+ p'' and lam_Q rho_a, from which the
-//       adjoints of pbar (lam_Q rho_a kappa0_a) and kappa0_a (lam_Q rho_a pbar)
-//       follow where they are gathered
+//       and per axis the adjoint of D^+ p'' and lam_Q rho_a A, from which the
+//       adjoints of pbar (lam_Q rho_a A kappa0_a) and kappa0_a
+//       (lam_Q rho_a A pbar) follow where they are gathered
 //   A_rcv  lam_p[R] += trace_n - obs_n
 //   A2  pressure points: lam_p'' = lam_p - sum_a D^-(lam_D'_a) + means of lam_pbar,
 //       gradient from the velocity multipliers, then the pressure phase
 //       reversed: lam_S = -dt lam_p''/K, lam_K = dt S lam_p''/K^2,
-//       lam_p = lam_p'' + lam_K kappa0 kappa0 (1-2beta),
-//       grad += lam_K (1 + 2 kappa0 (1-2beta) p), lam_psi2 <- lam_S + b2 lam_psi2,
+//       lam_p = lam_p'' + lam_K kappa0 nlq,
+//       grad += lam_K (1 + 2 nlq p), lam_psi2 <- lam_S + b2 lam_psi2,
 //       lam_D_a = w2 lam_S + sum c2 lam_psi2 (new)
 //   A3  v points inside the grid: lam_v_a -= D^+(lam_D_a)
 // using (D^-)^T = -(D^+) and (D^+)^T = -(D^-).
@@ -220,7 +223,7 @@ __global__ void __launch_bounds__(kABX *kABY) adj_velocity(const AdjArgs A)
         const float pbar = 0.5f * (A.pp[idx] + A.pp[idx + o]);
         const float rho_a = 0.5f * (A.f.rho[idx] + A.f.rho[idx + o]);
         const float kap_a = 0.5f * (A.f.kap[idx] + A.f.kap[idx + o]);
-        const float Q = rho_a * (1.0f + kap_a * pbar);
+        const float Q = rho_a * (1.0f + (A.f.nlA * kap_a) * pbar);
         float lva = lv[a * st + idx];
         if (DEFER_A3) {
             lva -= dplus(A.lDp + a * st, g, A.f.g, A.f.g11, a, nd, idx);
@@ -238,7 +241,7 @@ __global__ void __launch_bounds__(kABX *kABY) adj_velocity(const AdjArgs A)
             ntst(&lm1[c], fmaf(q.x, lmn, lS));
         }
         oDv[idx] = lD;
-        oqr[idx] = lQ * rho_a;
+        oqr[idx] = (lQ * rho_a) * A.f.nlA;      // the multiplier's coefficient A folded in
     }
 }
 

@@ -11,6 +11,7 @@
 #include <new>
 #include <string>
 #include <thread>
+#include <unordered_map>
 #include <utility>
 #include <vector>
 
@@ -59,21 +60,38 @@ fw2_status validate_scalars(const fw2_domain_desc *d)
     if (d->ndim != 2 && d->ndim != 3) return fail(FW2_E_INVALID, "ndim must be 2 or 3");
     if (d->n_relax < 1 || d->n_relax > FW2_MAX_RELAX)
         return fail(FW2_E_INVALID, "n_relax must be in 1..8");
+    const bool slab = d->slab_nz != 0;
+    if (slab) {
+        if (d->ndim != 3) return fail(FW2_E_INVALID, "slab domains are 3D");
+        if (d->slab_nz < 0 || d->slab_nz > (1 << 20) || d->slab_z0 < 0 || d->slab_z0 + d->n[2] > d->slab_nz)
+            return fail(FW2_E_INVALID, "need 0 <= slab_z0 and slab_z0 + nz <= slab_nz <= 2^20");
+        if (d->n[2] < fw2::kHalo) return fail(FW2_E_INVALID, "a slab needs at least 4 planes");
+        if (!(d->fd_r > 0.0) || !(d->pml_cp > 0.0))
+            return fail(FW2_E_INVALID, "slabs need fd_r > 0 and pml_cp > 0 (the same constants in every slab)");
+    }
     for (int a = 0; a < 3; ++a) {
         const int64_t na = d->n[a];
         if (a < d->ndim) {
             if (na < 1 || na > (1 << 20)) return fail(FW2_E_INVALID, "grid size out of range");
             if (d->bound_cells[a] < 0 || d->trans_cells[a] < 0 || d->trans_cells[a] > d->bound_cells[a])
                 return fail(FW2_E_INVALID, "need 0 <= trans_cells <= bound_cells");
-            if (2 * (int64_t)d->bound_cells[a] > na)
+            if (2 * (int64_t)d->bound_cells[a] > (a == 2 && slab ? d->slab_nz : na))
                 return fail(FW2_E_INVALID, "boundary layers wider than the grid");
         } else if (na != 1) {
             return fail(FW2_E_INVALID, "n[2] must be 1 in 2D");
         }
     }
-    // the 3D sweeps address a padded plane with 32-bit byte offsets
-    if (d->ndim == 3 && (d->n[0] + 72) * (d->n[1] + 8) >= ((int64_t)1 << 29))
-        return fail(FW2_E_INVALID, "a 3D plane (nx x ny) must hold fewer than 2^29 points");
+    // the sweeps address a padded plane (pitch <= nx + 71 elements, ny + 8
+    // rows) with 32-bit byte offsets: below 2^30 points in 2D, 2^29 in 3D
+    if ((d->n[0] + 72) * (d->n[1] + 8) >= ((int64_t)1 << (d->ndim == 3 ? 29 : 30)))
+        return fail(FW2_E_INVALID, d->ndim == 3 ? "a 3D plane (nx x ny) must hold fewer than 2^29 points"
+                                                : "a 2D grid (nx x ny) must hold fewer than 2^30 points");
+    if (d->nonlinear_form != FW2_NL_PRINTED && d->nonlinear_form != FW2_NL_CUSTOM)
+        return fail(FW2_E_INVALID, "nonlinear_form must be 0 or 1");
+    if (d->nonlinear_form == FW2_NL_CUSTOM &&
+        !(std::isfinite(d->nl_A) && std::isfinite(d->nl_B0) && std::isfinite(d->nl_B1)))
+        return fail(FW2_E_INVALID, "nl_A, nl_B0, nl_B1 must be finite");
+    if (d->map_kind != FW2_HOST && d->map_kind != FW2_DEVICE) return fail(FW2_E_INVALID, "map_kind must be 0 or 1");
     if (!finite_pos(d->h) || !finite_pos(d->dt)) return fail(FW2_E_INVALID, "h and dt must be positive");
     if (!(d->pml_Rc > 0.0 && d->pml_Rc < 1.0)) return fail(FW2_E_INVALID, "pml_Rc must be in (0, 1)");
     if (d->pml_npoly < 1 || d->pml_npoly > 8) return fail(FW2_E_INVALID, "pml_npoly must be in 1..8");
@@ -133,26 +151,26 @@ void make_layout(const fw2_domain_desc *d, Layout *ly)
     ly->total = end;
 }
 
-double max_c(const fw2_domain_desc *d, int64_t npts)
+// (A, B0, B1) of the multipliers rho0 (1 + A kappa0 p), kappa0 (1 + kappa0 B p).
+void nl_coefficients(const fw2_domain_desc *d, double *A, double *B0, double *B1)
 {
-    double m = 0.0;
-    for (int64_t q = 0; q < npts; ++q) m = std::max(m, (double)d->c[q]);
-    return m;
-}
-
-double min_c(const fw2_domain_desc *d, int64_t npts)
-{
-    double m = HUGE_VAL;
-    for (int64_t q = 0; q < npts; ++q) m = std::min(m, (double)d->c[q]);
-    return m;
+    if (d->nonlinear_form == FW2_NL_CUSTOM) {
+        *A = d->nl_A;
+        *B0 = d->nl_B0;
+        *B1 = d->nl_B1;
+    } else {                       // Eqs. state1 / state2 as printed
+        *A = 1.0;
+        *B0 = 1.0;
+        *B1 = -2.0;
+    }
 }
 
 // Per-point weights: every point's r lies in [min c, max c] dt / h (a
 // velocity point's r^2 is a mean of two cells'), so the scheme is checked
 // at a sweep of r over that range with the weights of each r.
-bool local_stencil_stable(const fw2_domain_desc *d, int64_t npts)
+bool local_stencil_stable(const fw2_domain_desc *d, double cmin, double cmax)
 {
-    const double r0 = min_c(d, npts) * d->dt / d->h, r1 = max_c(d, npts) * d->dt / d->h;
+    const double r0 = cmin * d->dt / d->h, r1 = cmax * d->dt / d->h;
     const int K = 16;
     for (int k = 0; k <= K; ++k) {
         const double r = std::sqrt(r0 * r0 + (r1 * r1 - r0 * r0) * k / K);
@@ -192,6 +210,7 @@ struct fw2_domain {
     bool adjoint = false;
     fw2::AdjointBuffers adj;
     int64_t adj_pp_step = -1;        // step whose p'' and S the adjoint buffers hold
+    bool mid_step = false;           // fw2_step_phase ran the pressure phase of a step
     int64_t npts() const { return (int64_t)ly.geo.n[0] * ly.geo.n[1] * ly.geo.n[2]; }
 };
 
@@ -333,6 +352,49 @@ fw2_status transfer_fields(fw2_domain *d, uint32_t mask, void *buf, int32_t kind
     return FW2_OK;
 }
 
+// Planes of a slab's halo exchange (see fw2.h): for a pack, the planes the
+// neighbour on `side` needs from this slab; for an unpack, this slab's halo
+// planes on `side`.
+fw2::PlaneSet halo_planes(const fw2_domain *d, int kind, int side, bool unpack)
+{
+    const fw2::StepArgs &a = d->args;
+    const int64_t S = d->ly.geo.stride;
+    const int nz = d->ly.geo.n[2];
+    fw2::PlaneSet s;
+    std::memset(&s, 0, sizeof(s));
+    auto add = [&](const float *arr, int count) {
+        // low side: planes [0, count) packed, [-count, 0) unpacked;
+        // high side: [nz - count, nz) packed, [nz, nz + count) unpacked
+        const int z0 = side == FW2_LOW ? (unpack ? -count : 0) : (unpack ? nz : nz - count);
+        s.arr[s.n] = arr;
+        s.z0[s.n] = z0;
+        s.nz[s.n] = count;
+        s.total += count;
+        s.n++;
+    };
+    if (kind == FW2_HALO_P) {
+        add(a.p, fw2::kHalo);
+    } else if (kind == FW2_HALO_V) {
+        add(a.v + 2 * S, fw2::kHalo);     // v_z: the z stencil
+        add(a.v, 1);                      // v_x, v_y: the g_11 cross terms
+        add(a.v + S, 1);
+    } else {
+        add(a.rho, 1);
+        add(a.kap, 1);
+    }
+    return s;
+}
+
+fw2_status halo_check(const fw2_domain *d, int kind, int side)
+{
+    if (!d) return fail(FW2_E_STATE, "domain is NULL");
+    if (d->desc.slab_nz <= 0) return fail(FW2_E_UNSUPPORTED, "halo exchange is for slab domains");
+    if (kind != FW2_HALO_P && kind != FW2_HALO_V && kind != FW2_HALO_MEDIUM)
+        return fail(FW2_E_INVALID, "bad halo kind");
+    if (side != FW2_LOW && side != FW2_HIGH) return fail(FW2_E_INVALID, "side must be FW2_LOW or FW2_HIGH");
+    return FW2_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -367,20 +429,20 @@ fw2_status fw2_create_domain(const fw2_domain_desc *desc, void *dev_workspace, u
     const int nd = desc->ndim, L = desc->n_relax;
     const int64_t npts = (int64_t)g.n[0] * g.n[1] * g.n[2];
 
-    // Map checks and the largest sound speed (stencil r, Table 1 c_p).
-    for (int64_t q = 0; q < npts; ++q) {
-        if (!finite_pos(desc->c[q]) || !finite_pos(desc->rho[q]) || !std::isfinite(desc->beta[q]))
-            return fail(FW2_E_INVALID, "c and rho must be positive and finite, beta finite");
-        if (desc->label && desc->label[q] >= desc->n_labels) return fail(FW2_E_INVALID, "label >= n_labels");
+    // Host maps: checked here, with the largest and smallest sound speed
+    // (stencil r, Table 1 c_p, the per-point stability sweep).  Device maps
+    // are checked by the conversion kernel below.
+    const bool dev_maps = desc->map_kind == FW2_DEVICE;
+    double cmax = 0.0, cmin = HUGE_VAL;
+    if (!dev_maps) {
+        for (int64_t q = 0; q < npts; ++q) {
+            if (!finite_pos(desc->c[q]) || !finite_pos(desc->rho[q]) || !std::isfinite(desc->beta[q]))
+                return fail(FW2_E_INVALID, "c and rho must be positive and finite, beta finite");
+            if (desc->label && desc->label[q] >= desc->n_labels) return fail(FW2_E_INVALID, "label >= n_labels");
+            cmax = std::max(cmax, (double)desc->c[q]);
+            cmin = std::min(cmin, (double)desc->c[q]);
+        }
     }
-    const double cmax = max_c(desc, npts);
-    const double r = desc->fd_r > 0.0 ? desc->fd_r : cmax * desc->dt / desc->h;
-    double gw[4], g11;
-    fw2::stencil_weights(r, nd, gw, &g11);
-    const double r_run = cmax * desc->dt / desc->h;
-    if (desc->stencil_mode == FW2_STENCIL_GLOBAL ? fw2::stability_factor(r_run, nd, gw, g11) >= 1.0
-                                                 : !local_stencil_stable(desc, npts))
-        return fail(FW2_E_INVALID, "time step above the stability limit of the (8,4) scheme");
 
     fw2_domain *d = new (std::nothrow) fw2_domain();
     if (!d) return fail(FW2_E_NOMEM, "host allocation failed");
@@ -422,26 +484,49 @@ fw2_status fw2_create_domain(const fw2_domain_desc *desc, void *dev_workspace, u
     a.rho = rho;
     a.label = ly.label_off ? d->ws + ly.label_off : nullptr;
     a.n_labels = desc->n_labels;
-    for (int k = 0; k < 4; ++k) a.g[k] = (float)(gw[k] / desc->h);
-    a.g11 = (float)(g11 / desc->h);
-    a.dt = (float)desc->dt;
-    a.local_stencil = desc->stencil_mode == FW2_STENCIL_LOCAL ? 1 : 0;
-    {
-        double pw[4][4], g11s;
-        fw2::stencil_polynomials(nd, pw, &g11s);
-        for (int j = 0; j < 4; ++j)
-            for (int k = 0; k < 4; ++k) a.pw[j][k] = (float)(pw[j][k] / desc->h);
-        a.g11s = (float)(g11s / desc->h);
-        a.q2 = (float)((desc->dt / desc->h) * (desc->dt / desc->h));
-    }
+    double nlA, nlB0, nlB1;
+    nl_coefficients(desc, &nlA, &nlB0, &nlB1);
+    a.nlA = (float)nlA;
+    a.z_off = desc->slab_nz > 0 ? (int32_t)desc->slab_z0 : 0;
+    a.nz_glob = desc->slab_nz > 0 ? (int32_t)desc->slab_nz : g.n[2];
 
-    // Medium planes: kappa0 = 1/(rho c^2), kappa0 (1 - 2 beta), rho (FP64, stored FP32).
-    // Planes are converted in chunks of about 16 M points by up to 16 host
-    // threads (a share of the chunk's rows each) and each chunk is uploaded
-    // with one copy per array: the planes of a chunk are contiguous on the
-    // device.  Halo cells of the staging buffers are never written and stay
-    // zero.
-    {
+    // Medium planes: kappa0 = 1/(rho c^2), kappa0 B with B = B0 + B1 beta
+    // (1 - 2 beta as printed), rho (FP64, stored FP32).
+    if (dev_maps) {
+        // on the GPU, with the maps checked and c's extremes reduced there;
+        // three words past the step counter and flag hold the results
+        fw2::MediumArgs m;
+        m.geo = g;
+        m.c = desc->c;
+        m.rho = desc->rho;
+        m.beta = desc->beta;
+        m.label = desc->label;
+        m.kap = kap;
+        m.nlq = nlq;
+        m.rhop = rho;
+        m.labp = (uint8_t *)a.label;
+        m.B0 = nlB0;
+        m.B1 = nlB1;
+        m.n_labels = desc->n_labels;
+        m.stats = (unsigned int *)(d->ws + 16);
+        FW2_HIP_C(fw2::launch_medium(m, d->stream));
+        unsigned int st3[3] = {0, 0, 0};
+        FW2_HIP_C(hipMemcpyAsync(st3, m.stats, sizeof(st3), hipMemcpyDeviceToHost, d->stream));
+        FW2_HIP_C(hipStreamSynchronize(d->stream));
+        FW2_HIP_C(hipMemsetAsync(m.stats, 0, sizeof(st3), d->stream));
+        if (st3[2]) return cleanup(fail(FW2_E_INVALID, "c and rho must be positive and finite, beta finite, label < n_labels"));
+        float fmax, fmin;
+        const unsigned int bmin = 0x7f800000u - st3[1];
+        std::memcpy(&fmax, &st3[0], 4);
+        std::memcpy(&fmin, &bmin, 4);
+        cmax = fmax;
+        cmin = fmin;
+    } else {
+        // Planes are converted in chunks of about 16 M points by up to 16
+        // host threads (a share of the chunk's rows each) and each chunk is
+        // uploaded with one copy per array: the planes of a chunk are
+        // contiguous on the device.  Halo cells of the staging buffers are
+        // never written and stay zero.
         const size_t plane_n = (size_t)g.plane;
         const int nz = g.n[2];
         const int cz = (int)std::max<size_t>(1, std::min<size_t>((size_t)nz, ((size_t)1 << 24) / plane_n));
@@ -465,7 +550,7 @@ fw2_status fw2_create_domain(const fw2_domain_desc *desc, void *dev_workspace, u
                         const double c = desc->c[q], rr = desc->rho[q], b = desc->beta[q];
                         const double k0 = 1.0 / (rr * c * c);
                         hk[o] = (float)k0;
-                        hn[o] = (float)(k0 * (1.0 - 2.0 * b));
+                        hn[o] = (float)(k0 * (nlB0 + nlB1 * b));
                         hr[o] = (float)rr;
                         if (a.label) hl[o] = desc->label[q];
                     }
@@ -492,6 +577,26 @@ fw2_status fw2_create_domain(const fw2_domain_desc *desc, void *dev_workspace, u
             if (a.label)
                 FW2_HIP_C(hipMemcpy((uint8_t *)a.label + off, hl.data(), n, hipMemcpyHostToDevice));
         }
+    }
+
+    const double r = desc->fd_r > 0.0 ? desc->fd_r : cmax * desc->dt / desc->h;
+    double gw[4], g11;
+    fw2::stencil_weights(r, nd, gw, &g11);
+    const double r_run = cmax * desc->dt / desc->h;
+    if (desc->stencil_mode == FW2_STENCIL_GLOBAL ? fw2::stability_factor(r_run, nd, gw, g11) >= 1.0
+                                                 : !local_stencil_stable(desc, cmin, cmax))
+        return cleanup(fail(FW2_E_INVALID, "time step above the stability limit of the (8,4) scheme"));
+    for (int k = 0; k < 4; ++k) a.g[k] = (float)(gw[k] / desc->h);
+    a.g11 = (float)(g11 / desc->h);
+    a.dt = (float)desc->dt;
+    a.local_stencil = desc->stencil_mode == FW2_STENCIL_LOCAL ? 1 : 0;
+    {
+        double pw[4][4], g11s;
+        fw2::stencil_polynomials(nd, pw, &g11s);
+        for (int j = 0; j < 4; ++j)
+            for (int k = 0; k < 4; ++k) a.pw[j][k] = (float)(pw[j][k] / desc->h);
+        a.g11s = (float)(g11s / desc->h);
+        a.q2 = (float)((desc->dt / desc->h) * (desc->dt / desc->h));
     }
 
     // Relaxation tables per axis (Sec. 3.2, Sec. 3.3 / Table 1).
@@ -607,6 +712,7 @@ fw2_status fw2_step(fw2_domain *d, int32_t n)
 {
     if (!d) return fail(FW2_E_STATE, "domain is NULL");
     if (n < 0) return fail(FW2_E_INVALID, "n < 0");
+    if (d->mid_step) return fail(FW2_E_STATE, "a step is half done (fw2_step_phase): run its velocity phase first");
     if (n == 0) return FW2_OK;
     if (d->timing) {
         for (int32_t s = 0; s < n; ++s) {
@@ -768,6 +874,7 @@ fw2_status fw2_adjoint_begin(fw2_domain *d, void *dev_workspace, uint64_t bytes)
         return fail(FW2_E_UNSUPPORTED, "the adjoint is derived for the time-centred memory scheme");
     if (d->desc.stencil_mode != FW2_STENCIL_GLOBAL)
         return fail(FW2_E_UNSUPPORTED, "the adjoint is derived for global stencil weights");
+    if (d->desc.slab_nz > 0) return fail(FW2_E_UNSUPPORTED, "the adjoint runs on whole grids, not slabs");
     uint64_t need = 0;
     fw2_status st = fw2_adjoint_workspace_bytes(d, &need);
     if (st != FW2_OK) return st;
@@ -823,6 +930,97 @@ fw2_status fw2_adjoint_gradient(fw2_domain *d, float *dst, int32_t kind)
     if (st != FW2_OK) return st;
     FW2_HIP(hipStreamSynchronize(d->stream));
     return FW2_OK;
+}
+
+fw2_status fw2_label_relaxation_map(int64_t n_pts, int32_t n_relax, const double *maps, uint8_t *label,
+                                    double *table, int32_t *n_labels)
+{
+    if (!maps || !label || !table || !n_labels) return fail(FW2_E_INVALID, "NULL argument");
+    if (n_pts < 1) return fail(FW2_E_INVALID, "n_pts < 1");
+    if (n_relax < 1 || n_relax > FW2_MAX_RELAX) return fail(FW2_E_INVALID, "n_relax must be in 1..8");
+    const int nrow = 2 + 4 * n_relax;
+    // distinct rows are kept in `table`; a hash of each row's bit patterns
+    // (FNV-1a over its 8-byte words) finds candidates, compared bitwise
+    std::unordered_multimap<uint64_t, int> seen;
+    int count = 0, last = -1;
+    double row[2 + 4 * FW2_MAX_RELAX];
+    for (int64_t i = 0; i < n_pts; ++i) {
+        for (int q = 0; q < nrow; ++q) row[q] = maps[(int64_t)q * n_pts + i];
+        int lab = -1;
+        if (last >= 0 && std::memcmp(table + (size_t)last * nrow, row, (size_t)nrow * 8) == 0) {
+            lab = last;                      // neighbouring points mostly share a tissue
+        } else {
+            uint64_t hsh = 1469598103934665603ull;
+            for (int q = 0; q < nrow; ++q) {
+                uint64_t bits;
+                std::memcpy(&bits, &row[q], 8);
+                hsh = (hsh ^ bits) * 1099511628211ull;
+            }
+            auto range = seen.equal_range(hsh);
+            for (auto it = range.first; it != range.second && lab < 0; ++it)
+                if (std::memcmp(table + (size_t)it->second * nrow, row, (size_t)nrow * 8) == 0) lab = it->second;
+            if (lab < 0) {
+                if (count == FW2_MAX_LABELS) return fail(FW2_E_INVALID, "more than 256 distinct relaxation tuples");
+                lab = count++;
+                std::memcpy(table + (size_t)lab * nrow, row, (size_t)nrow * 8);
+                seen.emplace(hsh, lab);
+            }
+        }
+        label[i] = (uint8_t)lab;
+        last = lab;
+    }
+    *n_labels = count;
+    return FW2_OK;
+}
+
+fw2_status fw2_halo_bytes(const fw2_domain *d, int32_t kind, uint64_t *bytes)
+{
+    fw2_status st = halo_check(d, kind, FW2_LOW);
+    if (st != FW2_OK) return st;
+    if (!bytes) return fail(FW2_E_INVALID, "bytes is NULL");
+    const fw2::PlaneSet s = halo_planes(d, kind, FW2_LOW, false);
+    *bytes = (uint64_t)s.total * (uint64_t)d->ly.geo.n[0] * (uint64_t)d->ly.geo.n[1] * 4u;
+    return FW2_OK;
+}
+
+fw2_status fw2_halo_pack(fw2_domain *d, int32_t kind, int32_t side, void *dev_dst)
+{
+    fw2_status st = halo_check(d, kind, side);
+    if (st != FW2_OK) return st;
+    if (!dev_dst) return fail(FW2_E_INVALID, "dst is NULL");
+    FW2_HIP(fw2::launch_pack(halo_planes(d, kind, side, false), d->ly.geo, (float *)dev_dst, d->stream));
+    return FW2_OK;
+}
+
+fw2_status fw2_halo_unpack(fw2_domain *d, int32_t kind, int32_t side, const void *dev_src)
+{
+    fw2_status st = halo_check(d, kind, side);
+    if (st != FW2_OK) return st;
+    if (!dev_src) return fail(FW2_E_INVALID, "src is NULL");
+    FW2_HIP(fw2::launch_unpack(halo_planes(d, kind, side, true), d->ly.geo, (const float *)dev_src, d->stream));
+    return FW2_OK;
+}
+
+fw2_status fw2_step_phase(fw2_domain *d, int32_t phase)
+{
+    if (!d) return fail(FW2_E_STATE, "domain is NULL");
+    const int L = d->desc.n_relax, sch = d->desc.relax_scheme;
+    if (phase == FW2_PHASE_PRESSURE) {
+        if (d->mid_step) return fail(FW2_E_STATE, "the pressure phase of this step already ran");
+        FW2_HIP(fw2::launch_pressure(d->args, L, sch, d->kc, d->stream));
+        FW2_HIP(fw2::launch_sources(d->src, d->stream));
+        d->mid_step = true;
+        return FW2_OK;
+    }
+    if (phase == FW2_PHASE_VELOCITY) {
+        if (!d->mid_step) return fail(FW2_E_STATE, "run the pressure phase of the step first");
+        if (!d->args.rcv.step) FW2_HIP(fw2::launch_receivers(d->rcv, d->stream));
+        FW2_HIP(fw2::launch_velocity(d->args, L, sch, d->kc, d->stream));
+        d->mid_step = false;
+        d->step++;
+        return FW2_OK;
+    }
+    return fail(FW2_E_INVALID, "phase must be FW2_PHASE_PRESSURE or FW2_PHASE_VELOCITY");
 }
 
 fw2_status fw2_check_finite(fw2_domain *d, float limit)

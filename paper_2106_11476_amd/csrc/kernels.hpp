@@ -6,7 +6,9 @@
 // planes of `plane` = pitch * (ny + 8) elements (3D).  Element (x, y, z) is at
 // origin + z * plane + y * pitch + x, and the arrays are placed so that x = 0
 // of every row is 256-byte aligned.  The halo of p and v is never written, so
-// stencil taps read zero outside the grid without bounds checks.
+// stencil taps read zero outside the grid without bounds checks.  A slab of a
+// grid split along z is the exception: its z halo planes hold the
+// neighbouring slabs' planes, written by the halo exchange.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -51,7 +53,7 @@ struct StepArgs {
     float *psi1;             // psi1[a][nu] = psi1 + (a * L + nu) * stride
     float *psi2;
     const float *kap;        // kappa0 = 1 / (rho c^2)
-    const float *nlq;        // kappa0 (1 - 2 beta)
+    const float *nlq;        // kappa0 B, B = 1 - 2 beta as printed
     const float *rho;        // rho0
     const uint8_t *label;    // nullptr: a single relaxation tuple
     int32_t n_labels;
@@ -63,6 +65,13 @@ struct StepArgs {
     float g[4];              // g_m0 / h
     float g11;               // g_11 / h
     float dt;
+    // Momentum multiplier rho_a (1 + nlA kappa0_a pbar); nlA = 1 as printed.
+    // (The mass multiplier's coefficient is folded into nlq.)
+    float nlA;
+    // Slab of a grid split along z: local plane k is global plane k + z_off
+    // of nz_glob planes (the boundary layer and the last v_z sample follow
+    // the global index).  A whole grid has z_off = 0, nz_glob = n[2].
+    int32_t z_off, nz_glob;
     // Per-point stencil weights (local_stencil != 0): with s = r^2 of the
     // point, g_m0(s) / h = sum_k pw[m-1][k] s^k and g_11(s) / h = g11s * s;
     // a cell's s = q2 / (rho kappa0), q2 = (dt / h)^2.
@@ -143,6 +152,13 @@ hipError_t launch_adjoint_step(const StepArgs &f, const SparseArgs &src, const S
                                bool *pp_next);
 hipError_t launch_adjoint_gradient(const StepArgs &f, const AdjointBuffers &b, hipStream_t stream);
 
+// Per-dimension, per-phase launchers (step_p2/v2/p3/v3.hip), called by
+// launch_pressure / launch_velocity.
+hipError_t launch_pressure_2d(const StepArgs &a, int L, int scheme, const KernelConfig &kc, hipStream_t stream);
+hipError_t launch_velocity_2d(const StepArgs &a, int L, int scheme, const KernelConfig &kc, hipStream_t stream);
+hipError_t launch_pressure_3d(const StepArgs &a, int L, int scheme, const KernelConfig &kc, hipStream_t stream);
+hipError_t launch_velocity_3d(const StepArgs &a, int L, int scheme, const KernelConfig &kc, hipStream_t stream);
+
 // Launchers (kernels.hip).  All enqueue on `stream` and return the launch error.
 hipError_t launch_pressure(const StepArgs &a, int L, int scheme, const KernelConfig &kc, hipStream_t stream);
 hipError_t launch_velocity(const StepArgs &a, int L, int scheme, const KernelConfig &kc, hipStream_t stream);
@@ -151,5 +167,35 @@ hipError_t launch_receivers(const SparseArgs &s, hipStream_t stream);   // also 
 hipError_t launch_fill(float *dst, int64_t n, float value, hipStream_t stream);
 hipError_t launch_check(const float *p, const Geometry &g, float limit, int *flag, hipStream_t stream);
 hipError_t launch_set_counter(long long *counter, long long value, hipStream_t stream);
+
+// Halo planes of a slab (halo.hip).  A plane set lists `n` (array, first
+// plane, plane count) ranges; pack gathers their unpadded [ny][nx] planes in
+// order into dst, unpack scatters src back into the same planes.
+struct PlaneSet {
+    const float *arr[4];
+    int32_t z0[4];
+    int32_t nz[4];
+    int32_t n;
+    int32_t total;           // sum of nz
+};
+hipError_t launch_pack(const PlaneSet &s, const Geometry &g, float *dst, hipStream_t stream);
+hipError_t launch_unpack(const PlaneSet &s, const Geometry &g, const float *src, hipStream_t stream);
+
+// Medium from device maps (halo.hip): kappa0 = 1/(rho c^2), kappa0 (B0 + B1
+// beta) and rho into the padded arrays (FP64 arithmetic, FP32 results, the
+// host conversion's operation order), labels copied; stats[0] / [1] receive
+// the bits of the largest / smallest c (atomics on the bit patterns of
+// positive floats) and stats[2] a nonzero flag for an invalid sample.
+struct MediumArgs {
+    Geometry geo;
+    const float *c, *rho, *beta;
+    const uint8_t *label;    // nullptr: none
+    float *kap, *nlq, *rhop;
+    uint8_t *labp;           // nullptr: not stored
+    double B0, B1;
+    int32_t n_labels;
+    unsigned int *stats;     // [3], zeroed by the caller
+};
+hipError_t launch_medium(const MediumArgs &m, hipStream_t stream);
 
 }  // namespace fw2

@@ -19,6 +19,11 @@ FIELD_P, FIELD_V, FIELD_PSI1, FIELD_PSI2, FIELD_ALL = 1, 2, 4, 8, 15
 HOST, DEVICE = 0, 1
 RELAX_PRINTED, RELAX_CENTRED = 0, 1
 STENCIL_GLOBAL, STENCIL_LOCAL = 0, 1
+NL_PRINTED, NL_CUSTOM = 0, 1
+HALO_P, HALO_V, HALO_MEDIUM = 0, 1, 2
+LOW, HIGH = 0, 1
+PHASE_PRESSURE, PHASE_VELOCITY = 0, 1
+MAX_LABELS = 256
 
 EXPORTS = ["fw2_workspace_bytes", "fw2_create_domain", "fw2_add_source", "fw2_add_receivers",
            "fw2_step", "fw2_read_fields", "fw2_write_fields", "fw2_current_step",
@@ -27,7 +32,9 @@ EXPORTS = ["fw2_workspace_bytes", "fw2_create_domain", "fw2_add_source", "fw2_ad
            "fw2_batch_workspace_bytes", "fw2_batch_create", "fw2_batch_set_domains",
            "fw2_batch_step", "fw2_batch_set_tile", "fw2_batch_destroy",
            "fw2_state_bytes", "fw2_save_state", "fw2_load_state", "fw2_adjoint_workspace_bytes",
-           "fw2_adjoint_begin", "fw2_adjoint_step", "fw2_adjoint_gradient"]
+           "fw2_adjoint_begin", "fw2_adjoint_step", "fw2_adjoint_gradient",
+           "fw2_label_relaxation_map", "fw2_halo_bytes", "fw2_halo_pack", "fw2_halo_unpack",
+           "fw2_step_phase"]
 
 
 class Fw2Error(RuntimeError):
@@ -46,6 +53,9 @@ class DomainDesc(ctypes.Structure):
         ("c", ctypes.c_void_p), ("rho", ctypes.c_void_p), ("beta", ctypes.c_void_p),
         ("label", ctypes.c_void_p), ("n_labels", ctypes.c_int32), ("relax_table", ctypes.c_void_p),
         ("stream", ctypes.c_void_p),
+        ("nonlinear_form", ctypes.c_int32), ("nl_A", ctypes.c_double), ("nl_B0", ctypes.c_double),
+        ("nl_B1", ctypes.c_double), ("map_kind", ctypes.c_int32),
+        ("slab_z0", ctypes.c_int64), ("slab_nz", ctypes.c_int64),
     ]
 
 
@@ -86,6 +96,11 @@ def lib():
             "fw2_adjoint_begin": [vp, vp, u64],
             "fw2_adjoint_step": [vp, vp, vp, i64, vp],
             "fw2_adjoint_gradient": [vp, vp, i32],
+            "fw2_label_relaxation_map": [i64, i32, vp, vp, vp, ctypes.POINTER(i32)],
+            "fw2_halo_bytes": [vp, i32, ctypes.POINTER(u64)],
+            "fw2_halo_pack": [vp, i32, i32, vp],
+            "fw2_halo_unpack": [vp, i32, i32, vp],
+            "fw2_step_phase": [vp, i32],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -142,7 +157,32 @@ def make_desc(prob, stream=None):
     d.relax_table = host(table, np.float64)
     d.label = host(prob.label, np.uint8) if (prob.label is not None and d.n_labels > 1) else None
     d.stream = stream.value if isinstance(stream, ctypes.c_void_p) else stream
+    d.nonlinear_form = int(getattr(prob, "nonlinear_form", NL_PRINTED))
+    d.nl_A = float(getattr(prob, "nl_A", 1.0))
+    d.nl_B0 = float(getattr(prob, "nl_B0", 1.0))
+    d.nl_B1 = float(getattr(prob, "nl_B1", -2.0))
+    d.map_kind = HOST
+    d.slab_z0 = int(getattr(prob, "slab_z0", 0))
+    d.slab_nz = int(getattr(prob, "slab_nz", 0))
     return d, keep
+
+
+def label_relaxation_map(maps, n_relax):
+    """fw2_label_relaxation_map: dense per-point relaxation maps
+    ([2 + 4L] + grid, FP64) to (uint8 labels of the grid's shape, table
+    [n_labels][2 + 4L])."""
+    m = np.ascontiguousarray(np.asarray(maps, dtype=np.float64))
+    nrow = 2 + 4 * int(n_relax)
+    if m.shape[0] != nrow:
+        raise ValueError("maps must have 2 + 4L = %d parameter maps" % nrow)
+    npts = int(np.prod(m.shape[1:]))
+    label = np.empty(npts, np.uint8)
+    table = np.empty((MAX_LABELS, nrow), np.float64)
+    n = ctypes.c_int32(0)
+    _check(lib().fw2_label_relaxation_map(npts, int(n_relax), ctypes.c_void_p(m.ctypes.data),
+                                          ctypes.c_void_p(label.ctypes.data), ctypes.c_void_p(table.ctypes.data),
+                                          ctypes.byref(n)))
+    return label.reshape(m.shape[1:]), table[:int(n.value)].copy()
 
 
 def workspace_bytes(prob):
@@ -159,17 +199,34 @@ class Domain:
     torch device tensors held by this object for as long as the library may
     read them."""
 
-    def __init__(self, prob, device="cuda", stream=None):
+    def __init__(self, prob, device="cuda", stream=None, device_maps=False):
         import torch
         self.torch = torch
         self.device = torch.device(device)
         self.shape = tuple(int(s) for s in prob.shape)
         self.ndim = len(self.shape)
         self.L = int(prob.n_relax)
+        self.slab_z0 = int(getattr(prob, "slab_z0", 0))
+        self.slab_nz = int(getattr(prob, "slab_nz", 0))
         if stream is None:
             stream = torch.cuda.current_stream(self.device)
         self.stream = stream
         d, keep = make_desc(prob, ctypes.c_void_p(stream.cuda_stream))
+        if device_maps:
+            # c, rho, beta (and labels) handed over as device tensors; the
+            # library converts them on the GPU
+            grid = self.shape[::-1]
+            dev = {}
+            for name in ("c", "rho", "beta"):
+                dev[name] = torch.as_tensor(np.ascontiguousarray(np.asarray(getattr(prob, name), np.float32)
+                                                                 .reshape(grid)), device=self.device)
+            d.c, d.rho, d.beta = (ctypes.c_void_p(dev[n].data_ptr()).value for n in ("c", "rho", "beta"))
+            if d.label:
+                dev["label"] = torch.as_tensor(np.ascontiguousarray(np.asarray(prob.label, np.uint8).reshape(grid)),
+                                               device=self.device)
+                d.label = dev["label"].data_ptr()
+            d.map_kind = DEVICE
+            keep.append(dev)
         nbytes = ctypes.c_uint64(0)
         _check(lib().fw2_workspace_bytes(ctypes.byref(d), ctypes.byref(nbytes)))
         self.workspace_bytes = int(nbytes.value)
@@ -243,6 +300,21 @@ class Domain:
 
     def check_finite(self, limit=1e12):
         _check(lib().fw2_check_finite(self._h, float(limit)))
+
+    # -- slabs of a grid split along z -------------------------------------
+    def step_phase(self, phase):
+        _check(lib().fw2_step_phase(self._h, int(phase)))
+
+    def halo_numel(self, kind):
+        n = ctypes.c_uint64(0)
+        _check(lib().fw2_halo_bytes(self._h, int(kind), ctypes.byref(n)))
+        return int(n.value) // 4
+
+    def halo_pack(self, kind, side, dst):
+        _check(lib().fw2_halo_pack(self._h, int(kind), int(side), ctypes.c_void_p(dst.data_ptr())))
+
+    def halo_unpack(self, kind, side, src):
+        _check(lib().fw2_halo_unpack(self._h, int(kind), int(side), ctypes.c_void_p(src.data_ptr())))
 
     # -- state blocks and the discrete adjoint -----------------------------
     def state_bytes(self):

@@ -211,16 +211,24 @@ def test_cpml_reflection_table2_tissue_recorded(oracle_lib):
 
 # ------------------------------------------------ nonlinear steepening (E5) ---
 
-def test_nonlinear_plane_wave_matches_exact_simple_wave(oracle_lib):
+@pytest.mark.parametrize("form", ["printed", "westervelt"])
+def test_nonlinear_plane_wave_matches_exact_simple_wave(oracle_lib, form):
     """Sec. 4.5: lossless plane pulse (1 MHz, 4 cycles), 20 ppw, CFL 0.4.
     The waveform recorded at receiver 1 is propagated to receiver 2 with the
     exact pre-shock simple-wave solution of the same equations (each value
-    travels at 1/sqrt(rho(p) kappa(p)), Eqs. state1 / state2, so the
-    effective coefficient is beta - 1); at sigma ~ 0.35 the first four
-    harmonic levels agree within 1 dB.  With the nonlinear terms switched off
+    travels at 1/sqrt(rho(p) kappa(p))); at sigma ~ 0.35 the first four
+    harmonic levels agree within 1 dB.  As printed (Eqs. state1 / state2:
+    rho0 (1 + kappa0 p), kappa0 (1 + kappa0 (1 - 2 beta) p)) the effective
+    coefficient is beta - 1; the custom form A = 0, B = -2 beta (the
+    multipliers rho0 and kappa0 (1 - 2 beta kappa0 p)) gives beta itself, the
+    Westervelt value of Sec. 2.2.  With the nonlinear terms switched off
     (beta = 1/2 in Eq. general6 and amplitude far smaller) the second
     harmonic is absent, so the match is not a linear-propagation artefact."""
-    p0, f0, ppw, cfl, beta = 2e6, 1e6, 20, 0.4, 3.5
+    f0, ppw, cfl, beta = 1e6, 20, 0.4, 3.5
+    nl = (1.0, 1.0, -2.0) if form == "printed" else (0.0, 0.0, -2.0)
+    beta_eff = -(nl[0] + nl[1] + nl[2] * beta) / 2.0      # beta - 1, or beta
+    assert beta_eff == (beta - 1 if form == "printed" else beta)
+    p0 = 2e6 * 2.5 / beta_eff                               # the same sigma for both forms
     lam = ppw
     nb, ntr = 4 * lam, 3 * lam
     nx = 48 + 2 * nb
@@ -231,6 +239,8 @@ def test_nonlinear_plane_wave_matches_exact_simple_wave(oracle_lib):
     ny = y2 + 2 * lam + nb
     prob = W.homogeneous((nx, ny), L=1, row=W.lossless_row(1), nb=(nb, nb), ntr=(ntr, ntr), f0=f0,
                          ppw=ppw, cfl=cfl, beta=beta)
+    if form != "printed":
+        prob.nonlinear_form, (prob.nl_A, prob.nl_B0, prob.nl_B1) = 1, nl
     h, dt = prob.h, prob.dt
     npulse = W.pulse_length(dt, f0, 4)
     nt = int((y2 - ys) * h / C0 / dt) + npulse + 100
@@ -249,8 +259,8 @@ def test_nonlinear_plane_wave_matches_exact_simple_wave(oracle_lib):
     t = (np.arange(nt) + 1) * dt
     kap0 = 1.0 / (1000.0 * C0 ** 2)
     dist = (y2 - y1) * h
-    pex = physics.simple_wave_propagate(t, tr[:, 0], dist, 1000.0, kap0, beta)
-    sigma = (beta - 1) * p0 * kap0 * (2 * np.pi * f0 / C0) * dist
+    pex = physics.simple_wave_propagate(t, tr[:, 0], dist, 1000.0, kap0, beta, nl)
+    sigma = beta_eff * p0 * kap0 * (2 * np.pi * f0 / C0) * dist
     assert 0.3 < sigma < 0.45
     N = 8 * nt
     f = np.fft.rfftfreq(N, dt)
@@ -258,6 +268,14 @@ def test_nonlinear_plane_wave_matches_exact_simple_wave(oracle_lib):
     for n in range(1, 5):
         k = np.argmin(np.abs(f - n * f0))
         assert abs(20 * np.log10(F2[k] / FE[k])) < 1.0, n
+    if form != "printed":
+        # the wrong coefficient (beta - 1, the printed form's) misses the
+        # harmonics of this run: the pin tells the two forms apart
+        pwr = physics.simple_wave_propagate(t, tr[:, 0], dist, 1000.0, kap0, beta)
+        FW = np.abs(np.fft.rfft(pwr, N))
+        k2 = np.argmin(np.abs(f - 2 * f0))
+        assert abs(20 * np.log10(F2[k2] / FW[k2])) > 2.0
+        return
     # the generated second harmonic is a real nonlinear effect
     prob.beta = np.full(prob.c.shape, 0.5, np.float32)
     prob.signals = (sig * 1e-3)[None].astype(np.float32)

@@ -77,6 +77,10 @@ class Problem:
     fd_r: float = 0.0                        # 0: largest c * dt / h
     relax_scheme: int = 1                    # 0: printed recursion, 1: time-centred
     stencil_mode: int = 0                    # 0: one global r, 1: r of the local sound speed
+    nonlinear_form: int = 0                  # 0: multipliers as printed; 1: the coefficients below
+    nl_A: float = 1.0                        # rho0 (1 + A kappa0 p)
+    nl_B0: float = 1.0                       # kappa0 (1 + kappa0 (B0 + B1 beta) p)
+    nl_B1: float = -2.0
     src_idx: np.ndarray = field(default_factory=lambda: np.zeros(0, np.int64))
     src_sig: np.ndarray = field(default_factory=lambda: np.zeros(0, np.int32))
     src_w: np.ndarray = field(default_factory=lambda: np.zeros(0, np.float32))
