@@ -2,19 +2,23 @@
 """Benchmark of the Fullwave 2 time stepper on one MI355X.
 
 A step is one time step of the whole hot path: pressure kernel, sources,
-receivers, velocity kernel, over the heterogeneous abdominal-wall-like 2D
-workload (4096 x 2048 points including the 4-wavelength boundary, L = 4
-relaxation mechanisms, 9 tissue labels, 128-element array, 3 MHz).
+receivers, velocity kernel.  The headline workload is the largest one that
+fits one GPU: the 3D transcranial-like cube (1024^3 points including the
+4-wavelength boundary, L = 2 relaxation mechanisms, 2 tissue labels, a
+focused spherical-cap source, 1 MHz).
 
 Prints one JSON line: Gpoint-updates/s over the timed steps, the roofline of
 the dominant kernel (HIP-event durations on the domain's stream, algorithmic
-bytes per launch), batched-serving sims/s and p50/p99 latency against the
-plain one-at-a-time solver, the sound-speed gradient of one shot of the
-1536^2 inversion workload (checkpointed forward + reverse steps, with the
-reverse step's own roofline), the same workload with per-point stencil
-weights, and the FP64 CPU oracle timed on a bounded sample.
+bytes per launch), the same cube with per-point stencil weights, one GPU's
+slab of that cube split along z with its halo exchange timed, the 2D
+abdominal-wall workload (4096 x 2048, L = 4, 12000 steps) as a sub-object,
+batched-serving sims/s and p50/p99 latency against the plain one-at-a-time
+solver, the sound-speed gradient of one shot of the 1536^2 inversion workload
+(checkpointed forward + reverse steps, with the reverse step's own
+roofline), the FP64 CPU oracle timed on a bounded sample (all host threads,
+and one thread), and the paper's own runtimes as context.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload abdominal_2d|plain_2d|skull_3d]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload skull_3d|abdominal_2d|plain_2d]
 """
 import argparse
 import json
@@ -28,16 +32,36 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, 8 TB/s
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2106_11476_amd", "csrc", "kernels.hip")
-ADJOINT_SOURCE = os.path.join(ROOT, "paper_2106_11476_amd", "csrc", "adjoint.hip")
+XGMI_LINK_GBS = 153.0   # one xGMI link, one direction
+CSRC = os.path.join(ROOT, "paper_2106_11476_amd", "csrc")
+# the step kernels are templates in step_kernels.hpp over the layout of kernels.hpp
+KERNEL_SOURCE = [os.path.join(CSRC, "step_kernels.hpp"), os.path.join(CSRC, "kernels.hpp")]
+ADJOINT_SOURCE = os.path.join(CSRC, "adjoint.hip")
 ADJOINT_WORKLOAD = "inversion_2d_1536"
 PROFILES = os.path.join(ROOT, "profiles")
 
+# The paper's own runtimes (Sec. 4.6, Fig. 6): context, not the target.
+PAPER_CONTEXT = {
+    "source": "Sec. 4.6 (computational performance), Fig. 6",
+    "hardware": "1x NVIDIA RTX 4090 (24 GB), CUDA 12.6",
+    "precision": "not stated",
+    "settings": "12 ppw, CFL 0.4, N = 2 relaxation mechanisms",
+    "saturated_gcells_per_s_2d": 1.5,
+    "saturated_gcells_per_s_3d": 0.75,
+    "grid_1024x1024_s_per_1000_steps": 0.667,
+    "grid_2048x2048_s_per_1000_steps": 2.74,
+    "grid_256x256x256_s_per_1000_steps": 22.6,
+}
 
-def kernel_source_sha(path=KERNEL_SOURCE):
+
+def kernel_source_sha(path=None):
     import hashlib
-    with open(path, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+    paths = KERNEL_SOURCE if path is None else ([path] if isinstance(path, str) else list(path))
+    h = hashlib.sha256()
+    for p in paths:
+        with open(p, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def _profile_values(path):
@@ -109,13 +133,51 @@ def make_workload(name, n3d=1024, relax=None):
     raise SystemExit("unknown workload %s, or one without a --relax option" % name)
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+_ORACLE_SAMPLE = r"""
+import json, sys, time
+sys.path.insert(0, %r)
+import workloads as W
+from oracle import solver
+prob = W.skull_3d(n=96, nb=12, ntr=9) if %r else W.abdominal_2d(nx=512, ny=512)
+maps = solver.coefficient_maps(prob)
+st = solver.State(maps.ndim, maps.L, maps.grid)
+t0 = time.perf_counter(); solver.run(prob, 1, st, maps, record=False); per = time.perf_counter() - t0
+k = int(max(1, min(200, %r / max(per, 1e-6))))
+t0 = time.perf_counter(); solver.run(prob, k, st, maps, record=False); el = time.perf_counter() - t0
+print(json.dumps({"value": prob.npts * k / el / 1e9, "threads": solver.threads(),
+                  "sample": "%%d steps of the full %%s grid, %%.1f s" %% (k, prob.name, el)}))
+"""
+
+
+def single_thread_oracle(three_d, target_s=8.0):
+    """The oracle on one host thread, in a child process (OMP_NUM_THREADS=1;
+    the child touches no GPU): a bounded sample of the same recipe."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    code = _ORACLE_SAMPLE % (ROOT, bool(three_d), float(target_s))
+    out = subprocess.check_output([sys.executable, "-c", code], env=env, timeout=600)
+    r = json.loads(out.decode().strip().splitlines()[-1])
+    return {"value": round(r["value"], 6), "unit": "Gpoint-updates/s", "cores": r["threads"], "sample": r["sample"]}
+
+
 def cpu_baseline(prob, target_s=15.0):
     """The FP64 oracle, as is, on the same workload: a bounded number of
-    steps on the full grid from the zero state (setup not timed).  For the
-    3D cube, whose FP64 state does not fit host memory, the same recipe on a
-    192^3 cube is the sample."""
+    steps on the full grid from the zero state (setup not timed), on all host
+    threads; plus a one-thread sample.  For the 3D cube, whose FP64 state
+    does not fit host memory, the same recipe on a 192^3 cube is the sample."""
     from oracle import solver
-    if prob.ndim == 3 and prob.npts > 192 ** 3:
+    three_d = prob.ndim == 3
+    if three_d and prob.npts > 192 ** 3:
         import workloads as W
         prob = W.skull_3d(n=192, nb=24, ntr=18)
     maps = solver.coefficient_maps(prob)
@@ -127,9 +189,16 @@ def cpu_baseline(prob, target_s=15.0):
     t0 = time.perf_counter()
     solver.run(prob, k, st, maps, record=False)
     el = time.perf_counter() - t0
-    return {"value": prob.npts * k / el / 1e9, "unit": "Gpoint-updates/s", "cores": solver.threads(),
-            "kind": "oracle",
-            "sample": "%d steps of the full %s grid (FP64 C stepper, OpenMP), %.1f s" % (k, prob.name, el)}
+    out = {"value": prob.npts * k / el / 1e9, "unit": "Gpoint-updates/s", "cores": solver.threads(),
+           "kind": "oracle", "cpu_model": cpu_model(), "host_threads": os.cpu_count(),
+           "sample": "%d steps of the full %s grid (FP64 C stepper, OpenMP, %d threads), %.1f s"
+                     % (k, prob.name, solver.threads(), el)}
+    del maps, st
+    try:
+        out["single_thread"] = single_thread_oracle(three_d)
+    except Exception as e:                      # reported, not fatal to the benchmark line
+        out["single_thread"] = {"error": str(e)[:200]}
+    return out
 
 
 def probe_copy(torch, dev, mib, reps=10):
@@ -151,22 +220,28 @@ def probe_copy(torch, dev, mib, reps=10):
     return {"bytes_per_copy": moved, "ms": round(ms, 4), "GBps": round(moved / ms / 1e6, 1), "reps": reps}
 
 
-def serving_leg(seed=4):
+STATED_SERVING_REQUESTS = 256     # the served workload's stream
+
+
+def serving_leg(seed=4, workload_requests=8, only_workload=False):
     """Continuous batching vs the plain one-at-a-time solver on four seeded
-    request streams of the heterogeneous 2D recipe: 8 requests at the served
-    workload's own sizes and step counts (1024^2-3072^2), 48 at 512^2-1024^2,
-    96 small 128^2-384^2 grids, and 48 small grids mixing every launch class
-    (3, 4 or 8 mechanisms; every third request with per-point stencil
-    weights).  Capacity: all requests queued at t = 0.  Latency: Poisson
-    arrivals at 1.2x the plain solver's capacity."""
+    request streams of the heterogeneous 2D recipe: `workload_requests` of
+    the served workload's requests (1024^2-3072^2 at their own step counts;
+    the stated stream has 256, the default 8 is a subsample), 48 at
+    512^2-1024^2, 96 small 128^2-384^2 grids, and 48 small grids mixing every
+    launch class (3, 4 or 8 mechanisms; every third request with per-point
+    stencil weights).  Capacity: all requests queued at t = 0.  Latency:
+    Poisson arrivals at 1.2x the plain solver's capacity.  target_met: the
+    batched capacity is at least twice the plain one."""
     import workloads as W
     from paper_2106_11476_amd import fw2, serve
     out = {}
-    for name, (n, sides, step, L_choices, local_every) in (
-            ("workload_1024_3072", (8, (1024, 3072), 256, (2, 3, 4), 0)),
-            ("heterogeneous_512_1024", (48, (512, 1024), 128, (2, 3, 4), 0)),
-            ("small_128_384", (96, (128, 384), 64, (2, 3, 4), 0)),
-            ("mixed_classes_128_384", (48, (128, 384), 64, (3, 4, 8), 3))):
+    streams = [("workload_1024_3072", (workload_requests, (1024, 3072), 256, (2, 3, 4), 0))]
+    if not only_workload:
+        streams += [("heterogeneous_512_1024", (48, (512, 1024), 128, (2, 3, 4), 0)),
+                    ("small_128_384", (96, (128, 384), 64, (2, 3, 4), 0)),
+                    ("mixed_classes_128_384", (48, (128, 384), 64, (3, 4, 8), 3))]
+    for name, (n, sides, step, L_choices, local_every) in streams:
         raw = W.serving_requests(n=n, seed=seed, sides=sides, side_step=step, L_choices=L_choices)
         if local_every:
             for i, (p, _, _) in enumerate(raw):
@@ -199,10 +274,14 @@ def serving_leg(seed=4):
             "capacity_gpoint_updates_per_s": {"plain": round(upd / p0.makespan / 1e9, 3),
                                               "batched": round(upd / b0.makespan / 1e9, 3)},
             "capacity_speedup": round(p0.makespan / b0.makespan, 3),
+            "target_met": bool(p0.makespan / b0.makespan >= 2.0),
             "capacity_host_s": {"plain": p0.summary()["host_s"], "batched": b0.summary()["host_s"]},
             "poisson_rate_per_s": round(lam, 3),
             "poisson": {"plain": pl.summary(), "batched": bt.summary()},
         }
+        if name == "workload_1024_3072":
+            out[name]["stated_stream_requests"] = STATED_SERVING_REQUESTS
+            out[name]["subsample"] = n < STATED_SERVING_REQUESTS
     return out
 
 
@@ -458,22 +537,145 @@ def summarize_adjoint(stats_db, fetch_db, write_db, copy_bytes, commands):
     print("profiles written to", PROFILES)
 
 
+def slab_leg(prob, steps=20, warmup=3, planes=128):
+    """One GPU's share of the cube split along z into slabs of `planes`
+    planes (the 1024^3 cube over 8 GPUs: 1024 x 1024 x 128 each): three
+    consecutive slabs around the middle of the cube, stepped with the halo
+    exchange after each phase (pack into a face buffer, unpack into the
+    neighbour's halo; on several GPUs the face would cross xGMI between the
+    two).  HIP events on the slabs' stream time the decomposed step, the step
+    kernels alone and the exchange alone."""
+    import torch
+    from paper_2106_11476_amd import fw2, slab
+    dev = torch.device("cuda:0")
+    nx, ny, nz = prob.shape
+    mid = nz // 2 - planes // 2
+    bounds = [0, mid - planes, mid, mid + planes, mid + 2 * planes, nz]
+    stream = torch.cuda.Stream(device=dev)
+    with torch.cuda.stream(stream):
+        ss = slab.SlabSet(prob, bounds, device=dev, stream=stream, cap_steps=2 * steps + warmup + 4, only=[1, 2, 3])
+    ss.step(warmup)
+    stream.synchronize()
+
+    def timed(fn):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            fn()
+        e1.record(stream)
+        stream.synchronize()
+        return e0.elapsed_time(e1) / steps            # ms per step of the three slabs
+
+    def kernels_only():
+        for d in ss.domains:
+            d.step_phase(fw2.PHASE_PRESSURE)
+        for d in ss.domains:
+            d.step_phase(fw2.PHASE_VELOCITY)
+
+    def exchange_only():
+        ss.exchange(fw2.HALO_P)
+        ss.exchange(fw2.HALO_V)
+
+    t_full = timed(lambda: ss.step(1))
+    t_kern = timed(kernels_only)
+    t_xch = timed(exchange_only)
+    face_p = ss.domains[1].halo_numel(fw2.HALO_P) * 4
+    face_v = ss.domains[1].halo_numel(fw2.HALO_V) * 4
+    for d in ss.domains:
+        d.check_finite(1e9)
+    ss.destroy()
+    npts = nx * ny * planes
+    n_if = 2                                            # interfaces between the three slabs
+    xch_per_slab = t_xch / n_if                         # a middle slab takes part in two
+    moved = n_if * 2 * (face_p + face_v) * 4            # each face packed and unpacked: read + write twice
+    return {"slab_shape": [nx, ny, planes], "grid": list(prob.shape), "slabs_timed": 3,
+            "z_planes": [bounds[1], bounds[4]], "steps": steps,
+            "step_ms_per_slab": round(t_full / 3, 4),
+            "gpts_per_slab": round(npts / (t_full / 3 * 1e-3) / 1e9, 3),
+            "kernels_ms_per_slab": round(t_kern / 3, 4),
+            "exchange_ms_per_slab": round(xch_per_slab, 4),
+            "exchange_over_kernels": round(xch_per_slab / (t_kern / 3), 4),
+            "face_bytes_per_step": {"p": face_p, "v": face_v, "total": face_p + face_v},
+            "pack_unpack_GBps": round(moved / (t_xch * 1e-3) / 1e9, 1),
+            "xgmi_ms_per_face_per_step_at_153GBps": round((face_p + face_v) / (XGMI_LINK_GBS * 1e9) * 1e3, 4)}
+
+
+def measure(prob, K, Wm):
+    """The benchmark proper: Wm untimed steps, then K steps timed on the
+    host clock around fw2_step with HIP-event timing of both kernels on the
+    domain's stream."""
+    import torch
+    from paper_2106_11476_amd import fw2
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(device=dev)
+    t_setup = time.perf_counter()
+    dom = fw2.from_problem(prob, device=dev, stream=stream, cap_steps=K + Wm)
+    torch.cuda.synchronize(dev)
+    setup_s = time.perf_counter() - t_setup
+    dom.step(Wm)
+    torch.cuda.synchronize(dev)
+    dom.enable_kernel_timing(True)
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
+    dom.step(K)
+    torch.cuda.synchronize(dev)
+    el = time.perf_counter() - t0
+    ms, cnt = dom.get_kernel_timing()
+    dom.enable_kernel_timing(False)
+    dom.check_finite(1e9)
+    dom.destroy_domain()
+    npts = prob.npts
+    gpts = npts * K / el / 1e9
+    labels = prob.label is not None and np.asarray(prob.relax_table).shape[0] > 1
+    p_b, v_b, step_b = kernel_bytes(prob.ndim, prob.n_relax, labels)
+    avg = [ms[0] / max(cnt[0], 1), ms[1] / max(cnt[1], 1)]     # ms per launch
+    dom_k = 0 if avg[0] >= avg[1] else 1
+    kb = (p_b, v_b)[dom_k] * npts
+    achieved = kb / (avg[dom_k] * 1e-3) / 1e9
+    kname = ("pressure_kernel", "velocity_kernel")[dom_k]
+    roof = {"bound": "hbm", "kernel": kname,
+            "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic(kname, prob.name),
+            "alg_bytes_per_point": (p_b, v_b)[dom_k], "points_per_launch": npts,
+            "launch_ms": round(avg[dom_k], 5),
+            "other_kernel_ms": round(avg[1 - dom_k], 5),
+            "step_alg_bytes_per_point": step_b,
+            "step_frac": round(gpts * step_b / HBM_PEAK_GBS, 4)}
+    return {"value": round(gpts, 3), "steps": K, "warmup": Wm, "ms_per_step": round(el / K * 1e3, 5),
+            "config": {"workload": prob.name, "grid": list(prob.shape), "points": npts,
+                       "relax_mechanisms": prob.n_relax,
+                       "labels": int(np.asarray(prob.relax_table).shape[0]),
+                       "relax_scheme": "centred" if prob.relax_scheme == 1 else "printed",
+                       "parallelism": "single GPU"},
+            "roofline": roof,
+            # host-side setup (FP64 coefficients, uploads, sources, receivers); not in the timed region
+            "setup_s": round(setup_s, 3)}
+
+
 def main():
     global PROFILES
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=12000)
-    ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--workload", default="abdominal_2d")
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (default 30 for skull_3d, 12000 in 2D)")
+    ap.add_argument("--warmup", type=int, default=None, help="untimed steps (default 5 for skull_3d, 200 in 2D)")
+    ap.add_argument("--workload", default="skull_3d")
     ap.add_argument("--n3d", type=int, default=1024, help="cube side of the skull_3d workload")
     ap.add_argument("--relax", type=int, default=None,
                     help="relaxation mechanisms (abdominal_2d: 3..8, default 4; skull_3d: 2 or 5..8, default 2)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true", help="skip the batched-serving leg")
+    ap.add_argument("--serving-requests", type=int, default=8,
+                    help="requests of the served workload's stream (the stated stream has 256)")
+    ap.add_argument("--serving-only-workload", action="store_true",
+                    help="serving leg: only the served workload's stream")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint (gradient) leg")
     ap.add_argument("--adjoint-steps", type=int, default=6000, help="steps of the adjoint leg's shot")
     ap.add_argument("--no-local-stencil", action="store_true",
                     help="skip the leg with per-point stencil weights")
+    ap.add_argument("--no-slab", action="store_true", help="skip the slab (one GPU's share) leg")
+    ap.add_argument("--no-abdominal", action="store_true",
+                    help="with the 3D headline, skip the 2D abdominal-wall sub-object")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first time a plain device copy of this size (bandwidth reference, "
                          "and the known-size kernel for scaling HBM counters)")
@@ -505,71 +707,51 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_2106_11476_amd import fw2
 
     dev = torch.device("cuda:0")
     copy_probe = None
     if args.copy_probe_mib > 0:
         copy_probe = probe_copy(torch, dev, args.copy_probe_mib)
+    three_d = args.workload == "skull_3d"
+    K = args.steps if args.steps is not None else (30 if three_d else 12000)
+    Wm = args.warmup if args.warmup is not None else (5 if three_d else 200)
     prob = make_workload(args.workload, args.n3d, args.relax)
-    K, Wm = int(args.steps), int(args.warmup)
-    stream = torch.cuda.Stream(device=dev)
-    t_setup = time.perf_counter()
-    dom = fw2.from_problem(prob, device=dev, stream=stream, cap_steps=K + Wm)
-    torch.cuda.synchronize(dev)
-    setup_s = time.perf_counter() - t_setup
-    dom.step(Wm)
-    torch.cuda.synchronize(dev)
-
-    dom.enable_kernel_timing(True)
-    torch.cuda.synchronize(dev)
-    t0 = time.perf_counter()
-    dom.step(K)
-    torch.cuda.synchronize(dev)
-    el = time.perf_counter() - t0
-    ms, cnt = dom.get_kernel_timing()
-    dom.enable_kernel_timing(False)
-    dom.check_finite(1e9)
-
-    npts = prob.npts
-    gpts = npts * K / el / 1e9
-    labels = prob.label is not None and np.asarray(prob.relax_table).shape[0] > 1
-    p_b, v_b, step_b = kernel_bytes(prob.ndim, prob.n_relax, labels)
-    avg = [ms[0] / max(cnt[0], 1), ms[1] / max(cnt[1], 1)]     # ms per launch
-    dom_k = 0 if avg[0] >= avg[1] else 1
-    kb = (p_b, v_b)[dom_k] * npts
-    achieved = kb / (avg[dom_k] * 1e-3) / 1e9
-    roof = {"bound": "hbm", "kernel": ("pressure_kernel", "velocity_kernel")[dom_k],
-            "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic(("pressure_kernel", "velocity_kernel")[dom_k], prob.name),
-            "alg_bytes_per_point": (p_b, v_b)[dom_k], "launch_ms": round(avg[dom_k], 5),
-            "other_kernel_ms": round(avg[1 - dom_k], 5),
-            "step_alg_bytes_per_point": step_b,
-            "step_frac": round(gpts * step_b / HBM_PEAK_GBS, 4)}
-    out = {"metric": "Gpoint-updates/s", "value": round(gpts, 3), "unit": "Gpoint-updates/s",
-           "n_gpus": 1, "steps": K, "warmup": Wm, "ms_per_step": round(el / K * 1e3, 5),
+    head = measure(prob, K, Wm)
+    out = {"metric": "Gpoint-updates/s", "value": head["value"], "unit": "Gpoint-updates/s",
+           "n_gpus": 1, "steps": K, "warmup": Wm, "ms_per_step": head["ms_per_step"],
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-           "data": "synthetic",
-           "config": {"workload": prob.name, "grid": list(prob.shape), "points": npts,
-                      "relax_mechanisms": prob.n_relax,
-                      "labels": int(np.asarray(prob.relax_table).shape[0]),
-                      "relax_scheme": "centred" if prob.relax_scheme == 1 else "printed",
-                      "parallelism": "single GPU"},
-           "roofline": roof,
-           # host-side setup (FP64 coefficients, uploads, sources, receivers); not in the timed region
-           "setup_s": round(setup_s, 3)}
+           "data": "synthetic", "config": head["config"], "roofline": head["roofline"],
+           "setup_s": head["setup_s"]}
+    print("[bench] headline %s: %.3f Gpoint-updates/s" % (prob.name, head["value"]), file=sys.stderr, flush=True)
     if copy_probe is not None:
         out["copy_probe"] = copy_probe
-    dom.destroy_domain()
     if not args.no_local_stencil:
         out["local_stencil"] = local_stencil_leg(prob, max(1, min(K, 2000)))
-    if not args.no_serving and args.workload != "skull_3d":
-        out["serving"] = serving_leg()
-    if not args.no_adjoint and args.workload != "skull_3d":
-        out["adjoint"] = adjoint_leg(steps=args.adjoint_steps)
-    if not args.no_cpu_baseline:
+    if three_d and not args.no_slab and prob.shape[2] >= 512:
+        out["slab"] = slab_leg(prob)
+        print("[bench] slab leg done", file=sys.stderr, flush=True)
+    if three_d and not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob)
+        print("[bench] cpu baseline done", file=sys.stderr, flush=True)
+    if three_d:
+        del prob
+    if three_d and not args.no_abdominal:
+        p2 = make_workload("abdominal_2d")
+        sub = measure(p2, 12000, 200)
+        if not args.no_local_stencil:
+            sub["local_stencil"] = local_stencil_leg(p2, 2000)
+        out["workloads"] = {p2.name: sub}
+        print("[bench] 2D workload done", file=sys.stderr, flush=True)
+    if not args.no_serving:
+        out["serving"] = serving_leg(workload_requests=args.serving_requests,
+                                     only_workload=args.serving_only_workload)
+        print("[bench] serving leg done", file=sys.stderr, flush=True)
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_leg(steps=args.adjoint_steps)
+        print("[bench] adjoint leg done", file=sys.stderr, flush=True)
+    if not three_d and not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(prob)
+    out["paper_context"] = PAPER_CONTEXT
     print(json.dumps(out), flush=True)
 
 

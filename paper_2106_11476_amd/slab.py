@@ -24,8 +24,9 @@ import numpy as np
 from . import fw2
 
 
-def split_problem(prob, bounds):
-    """Slab problems of a 3D problem for z boundaries bounds = [0, z1, ..., nz].
+def split_problem(prob, bounds, only=None):
+    """Slab problems of a 3D problem for z boundaries bounds = [0, z1, ..., nz]
+    (only: indices of the slabs to build, default all).
 
     Each slab gets its planes of the maps, its sources and receivers (local
     flat indices), slab_z0 / slab_nz, and the stencil Courant number and
@@ -47,7 +48,7 @@ def split_problem(prob, bounds):
     src = np.asarray(prob.src_idx, np.int64)
     rcv = np.asarray(prob.rcv_idx, np.int64)
     slabs, cols = [], []
-    for k in range(len(b) - 1):
+    for k in (range(len(b) - 1) if only is None else only):
         z0, z1 = b[k], b[k + 1]
         s = copy.copy(prob)
         s.shape = (nx, ny, z1 - z0)
@@ -70,9 +71,11 @@ def split_problem(prob, bounds):
 
 
 class SlabSet:
-    """The slabs of one grid on one device, stepped with halo exchange."""
+    """The slabs of one grid on one device, stepped with halo exchange
+    (only: consecutive slab indices, to hold a part of the grid; its outer
+    faces then keep zero halos)."""
 
-    def __init__(self, prob, bounds, device="cuda", stream=None, cap_steps=None):
+    def __init__(self, prob, bounds, device="cuda", stream=None, cap_steps=None, only=None):
         import torch
         self.torch = torch
         self.device = torch.device(device)
@@ -80,7 +83,7 @@ class SlabSet:
         self.shape = tuple(int(s) for s in prob.shape)
         self.bounds = [int(x) for x in bounds]
         self.n_rcv = len(prob.rcv_idx)
-        probs, self.rcv_cols = split_problem(prob, bounds)
+        probs, self.rcv_cols = split_problem(prob, bounds, only)
         cap = cap_steps if cap_steps is not None else max(int(prob.n_steps), 1)
         self.domains = []
         for s in probs:
