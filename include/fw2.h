@@ -284,6 +284,20 @@ fw2_status fw2_batch_step(fw2_batch *b, int32_t n);
 fw2_status fw2_batch_set_tile(fw2_batch *b, int32_t cols, int32_t rows);
 void fw2_batch_destroy(fw2_batch *b);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops that must not call hipMalloc, harnesses that forbid
+ * it): fw2_batch_create without a workspace.  The batch uses the library's
+ * own table, a file-scope device array of sizeof the 64-domain table (45 KiB,
+ * one per GPU, held until the process ends), instead of caller memory; the
+ * call allocates no device memory.  max_domains is 1..64 (FW2_E_INVALID
+ * beyond: the table holds 64 domains).  The table is cleared by this call
+ * and rewritten by fw2_batch_set_domains; it keeps the last batch's contents
+ * otherwise.  One such batch per GPU at a time: while one exists on the
+ * current device another call returns FW2_E_STATE (calls that shared the
+ * table would race); fw2_batch_destroy frees it for the next.  Everything
+ * else is as for fw2_batch_create. */
+fw2_status fw2_batch_create_noalloc(int32_t max_domains, void *stream, fw2_batch **out);
+
 /* ---- Relaxation maps to labels -------------------------------------------
  * Sec. 3.2 gives every point its own 2 + 4L relaxation parameters; the library
  * stores a label per point and a table of the distinct tuples.  This call

@@ -2,7 +2,51 @@
 // persistent batch kernels.
 #include "step_kernels.hpp"
 
+#include <mutex>
+
+// Batch table of fw2_batch_create_noalloc: file-scope device memory, one copy
+// per GPU, held until the process ends.  In host code its name is only a
+// stand-in: the device address of each GPU's copy comes from
+// hipGetSymbolAddress with that GPU current (static_batch_table below).
+static __device__ __align__(256) unsigned char scratch[sizeof(fw2::BatchTable)];
+
 namespace fw2 {
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+void *g_static_ptr[kMaxDevices];       // device address of `scratch`, per device
+bool g_static_busy[kMaxDevices];       // a no-allocation batch holds the table
+
+}  // namespace
+
+hipError_t claim_static_batch_table(int device, BatchTable **table, bool *busy)
+{
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    *table = nullptr;
+    *busy = false;
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    if (!g_static_ptr[device]) {                  // once per device, with it current
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_static_ptr[device] = p;
+    }
+    if (g_static_busy[device]) {
+        *busy = true;
+        return hipSuccess;
+    }
+    g_static_busy[device] = true;
+    *table = (BatchTable *)g_static_ptr[device];
+    return hipSuccess;
+}
+
+void release_static_batch_table(int device)
+{
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    if (device >= 0 && device < kMaxDevices) g_static_busy[device] = false;
+}
 
 namespace {
 

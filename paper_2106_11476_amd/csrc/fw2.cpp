@@ -1051,6 +1051,7 @@ struct fw2_batch {
     int rows = 4;
     int bx = 256;
     unsigned classes = 0;               // launch classes present in the table (fw2::batch_class)
+    int static_device = -1;             // >= 0: the table is the library's own on this device
 };
 
 namespace {
@@ -1221,6 +1222,41 @@ fw2_status fw2_batch_set_tile(fw2_batch *b, int32_t cols, int32_t rows)
     return FW2_OK;
 }
 
+fw2_status fw2_batch_create_noalloc(int32_t max_domains, void *stream, fw2_batch **out)
+{
+    if (!out) return fail(FW2_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (max_domains < 1 || max_domains > fw2::kMaxBatch)
+        return fail(FW2_E_INVALID, "max_domains must be in 1..64 (the library's own table holds 64 domains)");
+    int device = -1;
+    FW2_HIP(hipGetDevice(&device));
+    fw2::BatchTable *table = nullptr;
+    bool busy = false;
+    FW2_HIP(fw2::claim_static_batch_table(device, &table, &busy));
+    if (busy) return fail(FW2_E_STATE, "another no-allocation batch holds this device's table");
+    fw2_batch *b = new (std::nothrow) fw2_batch();
+    if (!b) {
+        fw2::release_static_batch_table(device);
+        return fail(FW2_E_NOMEM, "host allocation failed");
+    }
+    fw2::prepare_batch_launches();
+    b->max_domains = max_domains;
+    b->dev = table;
+    b->static_device = device;
+    b->stream = (hipStream_t)stream;
+    std::memset(&b->host, 0, sizeof(b->host));
+    b->host.rows = b->rows;
+    // the table keeps the last batch's contents: start from the empty table
+    hipError_t e = hipMemcpy(b->dev, &b->host, sizeof(b->host), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        fw2::release_static_batch_table(device);
+        delete b;
+        return fail(FW2_E_HIP, std::string("hipMemcpy: ") + hipGetErrorString(e));
+    }
+    *out = b;
+    return FW2_OK;
+}
+
 void fw2_batch_destroy(fw2_batch *b)
 {
     if (!b) return;
@@ -1228,6 +1264,7 @@ void fw2_batch_destroy(fw2_batch *b)
     (void)batch_release(b);
     batch_drop_graph(b);
     if (b->capture) (void)hipStreamDestroy(b->capture);
+    if (b->static_device >= 0) fw2::release_static_batch_table(b->static_device);
     delete b;
 }
 

@@ -135,6 +135,11 @@ hipError_t launch_batch_step(const BatchTable *dev_table, int n_entries_max, int
 // Sizes the persistent grids of the batch kernels (occupancy queries); call
 // outside stream capture before the first batched step.
 void prepare_batch_launches();
+// The library's own batch table on `device` (the current device), for a
+// batch that allocates nothing: *busy is set (and *table left NULL) while
+// another such batch holds it.  Released by release_static_batch_table.
+hipError_t claim_static_batch_table(int device, BatchTable **table, bool *busy);
+void release_static_batch_table(int device);
 
 // Discrete adjoint of one step (adjoint.hip): device arrays of the adjoint
 // state (same layout as the forward state block) and the per-step temporaries.

@@ -34,7 +34,7 @@ EXPORTS = ["fw2_workspace_bytes", "fw2_create_domain", "fw2_add_source", "fw2_ad
            "fw2_state_bytes", "fw2_save_state", "fw2_load_state", "fw2_adjoint_workspace_bytes",
            "fw2_adjoint_begin", "fw2_adjoint_step", "fw2_adjoint_gradient",
            "fw2_label_relaxation_map", "fw2_halo_bytes", "fw2_halo_pack", "fw2_halo_unpack",
-           "fw2_step_phase"]
+           "fw2_step_phase", "fw2_batch_create_noalloc"]
 
 
 class Fw2Error(RuntimeError):
@@ -101,6 +101,7 @@ def lib():
             "fw2_halo_pack": [vp, i32, i32, vp],
             "fw2_halo_unpack": [vp, i32, i32, vp],
             "fw2_step_phase": [vp, i32],
+            "fw2_batch_create_noalloc": [i32, vp, ctypes.POINTER(vp)],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -435,18 +436,26 @@ class Domain:
 class Batch:
     """Batched stepping of several resident 2D domains (fw2_batch_*)."""
 
-    def __init__(self, max_domains=64, device="cuda", stream=None):
+    def __init__(self, max_domains=64, device="cuda", stream=None, noalloc=False):
+        """noalloc: fw2_batch_create_noalloc (the library's own table, no
+        workspace)."""
         import torch
         self.torch = torch
         self.device = torch.device(device)
         self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
-        nb = ctypes.c_uint64(0)
-        _check(lib().fw2_batch_workspace_bytes(int(max_domains), ctypes.byref(nb)))
-        self.workspace = torch.empty(int(nb.value), dtype=torch.uint8, device=self.device)
-        torch.cuda.synchronize(self.device)
         h = ctypes.c_void_p()
-        _check(lib().fw2_batch_create(int(max_domains), ctypes.c_void_p(self.workspace.data_ptr()),
-                                      int(nb.value), ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
+        if noalloc:
+            self.workspace = None
+            with torch.cuda.device(self.device):
+                _check(lib().fw2_batch_create_noalloc(int(max_domains), ctypes.c_void_p(self.stream.cuda_stream),
+                                                      ctypes.byref(h)))
+        else:
+            nb = ctypes.c_uint64(0)
+            _check(lib().fw2_batch_workspace_bytes(int(max_domains), ctypes.byref(nb)))
+            self.workspace = torch.empty(int(nb.value), dtype=torch.uint8, device=self.device)
+            torch.cuda.synchronize(self.device)
+            _check(lib().fw2_batch_create(int(max_domains), ctypes.c_void_p(self.workspace.data_ptr()),
+                                          int(nb.value), ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
         self._h = h
         self.max_domains = int(max_domains)
         self.domains = []
