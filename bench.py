@@ -396,6 +396,48 @@ def adjoint_leg(steps=6000, K=64, shot=31, timed_reverse=200):
                                  "traffic_bytes_per_point": measured_adjoint_traffic()}}
 
 
+def full_gradient_leg(n_shots=64, steps=6000, K=64):
+    """The inversion workload's whole gradient: the misfit summed over
+    n_shots shots (each source fired alone, every shot recorded on the 256
+    receivers), dJ/dc accumulated over the shots.  Per shot: the observed
+    traces from the true medium, the checkpointed forward and the backward.
+    Times the whole job on the host clock around each shot."""
+    import torch
+    import workloads as W
+    from paper_2106_11476_amd import adjoint, fw2
+    dev = torch.device("cuda:0")
+    total = None
+    J_sum = 0.0
+    t_obs = t_grad = 0.0
+    for shot in range(n_shots):
+        prob, c_true = W.inversion_2d(shot=shot, n_steps=steps)
+        truth = W.Problem(**{k: getattr(prob, k) for k in prob.__dataclass_fields__})
+        truth.c = c_true
+        torch.cuda.synchronize(dev)
+        t0 = time.perf_counter()
+        dom = fw2.from_problem(truth, device=dev, cap_steps=steps)
+        dom.step(steps)
+        torch.cuda.synchronize(dev)
+        obs = dom.trace[:steps].clone()
+        dom.destroy_domain()
+        t1 = time.perf_counter()
+        c = torch.tensor(np.asarray(prob.c, np.float64), requires_grad=True)
+        J = adjoint.misfit(c, obs, prob, steps, checkpoint_every=K)
+        J.backward()
+        torch.cuda.synchronize(dev)
+        t2 = time.perf_counter()
+        t_obs += t1 - t0
+        t_grad += t2 - t1
+        J_sum += float(J.item())
+        g = c.grad.numpy()
+        total = g.copy() if total is None else total + g
+    return {"workload": "inversion_2d_1536", "shots": n_shots, "receivers": 256, "steps": steps,
+            "checkpoint_every": K, "misfit_sum": J_sum, "gradient_finite": bool(np.isfinite(total).all()),
+            "gradient_rms": float(np.sqrt(np.mean(total ** 2))),
+            "observed_traces_s": round(t_obs, 3), "gradient_s": round(t_grad, 3),
+            "gradient_s_per_shot": round(t_grad / n_shots, 4)}
+
+
 def _db_rows(db, sql):
     import sqlite3
     con = sqlite3.connect(db)
@@ -671,6 +713,8 @@ def main():
                     help="serving leg: only the served workload's stream")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint (gradient) leg")
     ap.add_argument("--adjoint-steps", type=int, default=6000, help="steps of the adjoint leg's shot")
+    ap.add_argument("--adjoint-shots", type=int, default=0,
+                    help="also compute the whole gradient over this many shots (the workload has 64)")
     ap.add_argument("--no-local-stencil", action="store_true",
                     help="skip the leg with per-point stencil weights")
     ap.add_argument("--no-slab", action="store_true", help="skip the slab (one GPU's share) leg")
@@ -749,6 +793,9 @@ def main():
     if not args.no_adjoint:
         out["adjoint"] = adjoint_leg(steps=args.adjoint_steps)
         print("[bench] adjoint leg done", file=sys.stderr, flush=True)
+    if args.adjoint_shots > 0:
+        out["adjoint_full_gradient"] = full_gradient_leg(n_shots=args.adjoint_shots, steps=args.adjoint_steps)
+        print("[bench] full gradient done", file=sys.stderr, flush=True)
     if not three_d and not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob)
     out["paper_context"] = PAPER_CONTEXT

@@ -15,6 +15,16 @@ Reading used (see the design notes, "boundary geometry"):
 * kappa is unchanged (Table 1, target = initial value).
 All through the general formula X(s) = (X~ - X0) g(s) + X0.
 Profiles are directional: the x-derivative uses the x distance only.
+
+Two other readings are available for the reflection study only (the library
+and the workloads use reading A):
+* reading "B": the nu = 1 ramps run over the outer L_Bound only (the
+  polynomial and linear functions of Sec. 3.3 take L_B = L_Bound), the
+  target d~ still with L_CPML as Table 1 prints it;
+* reading "A_kappa": reading A with the target of each derivative scaled by
+  its own kappa (d~_i = kappa_i d~), which keeps the ratio of the two
+  stretch factors, and so the impedance, at the interior's value deep in the
+  layer when kappa_1 != kappa_2.
 """
 import numpy as np
 
@@ -58,11 +68,12 @@ def boundary_distance(coord, n, nb):
     return np.minimum(s, float(nb))
 
 
-def profile(s_cells, h, nb, ntr, d0, a0, nu, c_p, R_c, N):
+def profile(s_cells, h, nb, ntr, d0, a0, nu, c_p, R_c, N, reading="A", kappa=1.0):
     """(d, alpha) of mechanism nu (1-based) at distance s_cells into the layer.
 
     d0, a0 are the local tissue values (Table 1 initial values); s_cells can be
-    an array broadcastable against d0/a0.
+    an array broadcastable against d0/a0.  reading and kappa: see the module
+    notes (kappa is the derivative's own kappa, used by reading "A_kappa").
     """
     s = np.asarray(s_cells, dtype=np.float64)
     if nb == 0:
@@ -70,8 +81,16 @@ def profile(s_cells, h, nb, ntr, d0, a0, nu, c_p, R_c, N):
             np.broadcast_to(a0, np.broadcast(s, a0).shape).astype(np.float64)
     if nu == 1:
         L = nb * h
-        x = s * h
         dt_ = d_target(c_p, R_c, N, L)
+        if reading == "A_kappa":
+            dt_ = dt_ * np.asarray(kappa, dtype=np.float64)
+        if reading == "B" and nb > ntr:
+            Lb = (nb - ntr) * h
+            x = np.maximum(s - ntr, 0.0) * h
+            return blend(d0, dt_, g_polynomial(x, Lb, N)), blend(a0, 0.0, g_linear(x, Lb))
+        if reading not in ("A", "A_kappa", "B"):
+            raise ValueError("unknown boundary reading %r" % (reading,))
+        x = s * h
         d = blend(d0, dt_, g_polynomial(x, L, N))
         a = blend(a0, 0.0, g_linear(x, L))
         return d, a

@@ -200,6 +200,9 @@ def coefficient_maps(prob):
 
     c_p = float(prob.pml_cp) if prob.pml_cp and prob.pml_cp > 0 else cmax
     Rc, N = float(prob.pml_Rc), int(prob.pml_npoly)
+    # boundary-layer reading: "A" (the library's); "B" and "A_kappa" serve the
+    # reflection study only (oracle.pml)
+    reading = getattr(prob, "pml_reading", "A")
 
     npts = int(np.prod(grid))
     m.ik1 = np.stack([1.0 / k1 for _ in range(ndim)])
@@ -218,12 +221,12 @@ def coefficient_maps(prob):
         s_half = _along(pml.boundary_distance(np.arange(n_a) + 0.5, n_a, nb), ndim, a)
         for nu in range(L):
             # nabla_2 at pressure points (integer positions along a)
-            dd, aa = pml.profile(s_int, m.h, nb, ntr, d2[nu], al2[nu], nu + 1, c_p, Rc, N)
+            dd, aa = pml.profile(s_int, m.h, nb, ntr, d2[nu], al2[nu], nu + 1, c_p, Rc, N, reading, k2)
             A, B = relaxation.memory_coefficients(k2, dd, aa, m.dt)
             m.a2[a, nu], m.b2[a, nu] = A, B
             m.e0_2[a, nu] = relaxation.centred_weights(k2, dd, aa, m.dt)[0]
             # nabla_1 at velocity points (half-integer positions along a)
-            dd, aa = pml.profile(s_half, m.h, nb, ntr, d1[nu], al1[nu], nu + 1, c_p, Rc, N)
+            dd, aa = pml.profile(s_half, m.h, nb, ntr, d1[nu], al1[nu], nu + 1, c_p, Rc, N, reading, k1)
             A, B = relaxation.memory_coefficients(k1, dd, aa, m.dt)
             m.a1[a, nu], m.b1[a, nu] = A, B
             m.e0_1[a, nu] = relaxation.centred_weights(k1, dd, aa, m.dt)[0]
@@ -426,6 +429,23 @@ def numpy_run(prob, n_steps, state=None, maps=None):
                 state.psi1[a, nu] = np.where(inside, state.psi1[a, nu], psi1_old[a][nu])
         state.step += 1
     return state, trace
+
+
+def stencil_maps(prob):
+    """The part of coefficient_maps that divergence() needs (grid, stencil
+    weights), without the per-point relaxation maps (large grids)."""
+    ndim = len(prob.shape)
+    m = Maps()
+    m.ndim, m.grid = ndim, tuple(prob.shape[::-1])
+    m.h, m.dt = float(prob.h), float(prob.dt)
+    m.stencil_mode = int(getattr(prob, "stencil_mode", 0))
+    if m.stencil_mode != 0:
+        return coefficient_maps(prob)
+    cmax = float(np.max(np.asarray(prob.c, dtype=np.float64)))
+    r = float(prob.fd_r) if prob.fd_r and prob.fd_r > 0 else cmax * m.dt / m.h
+    g, g11 = stencil.stencil_weights(r, ndim)
+    m.r, m.g, m.g11 = r, g / m.h, g11 / m.h
+    return m
 
 
 def divergence(v, maps):

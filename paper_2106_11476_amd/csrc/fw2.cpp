@@ -634,14 +634,17 @@ fw2_status fw2_create_domain(const fw2_domain_desc *desc, void *dev_workspace, u
         a.w1[ax] = a.w2[ax] = nullptr;
     }
 
-    d->kc = nd == 2 ? fw2::KernelConfig{1, 256, 4} : fw2::KernelConfig{2, 64, 64};
-    if (const char *ev = std::getenv("FW2_KERNEL_CONFIG")) {      // "variant,bx,rows" (tuning runs)
-        int v = 0, bx = 0, ry = 0;
-        const bool parsed = std::sscanf(ev, "%d,%d,%d", &v, &bx, &ry) == 3;
-        const bool ok2 = nd == 2 && (v == 0 || v == 1 || v == 2) && (bx == 64 || bx == 128 || bx == 256);
-        const bool ok3 = nd == 3 && (v == 0 || ((v == 1 || v == 2) && (bx == 16 || bx == 32 || bx == 64)));
+    d->kc = nd == 2 ? fw2::KernelConfig{1, 256, 4} : fw2::KernelConfig{3, 64, 64};
+    if (const char *ev = std::getenv("FW2_KERNEL_CONFIG")) {      // "variant,bx,rows[,by]" (tuning runs)
+        int v = 0, bx = 0, ry = 0, by = 0;
+        const int nparsed = std::sscanf(ev, "%d,%d,%d,%d", &v, &bx, &ry, &by);
+        const bool parsed = nparsed == 3 || nparsed == 4;
+        const bool ok2 = nd == 2 && by == 0 && (v == 0 || v == 1 || v == 2) && (bx == 64 || bx == 128 || bx == 256);
+        const bool tile3 = by == 0 ? (bx == 16 || bx == 32 || bx == 64)
+                                   : (v == 3 && ((bx == 64 && by == 4) || (bx == 32 && by == 8)));
+        const bool ok3 = nd == 3 && (v == 0 || ((v >= 1 && v <= 3) && tile3));
         if (parsed && (ok2 || ok3) && ry >= 1 && ry <= 1024)
-            d->kc = fw2::KernelConfig{v, bx, ry};
+            d->kc = fw2::KernelConfig{v, bx, ry, by};
     }
 
     std::memset(&d->src, 0, sizeof(d->src));

@@ -92,11 +92,15 @@ struct StepArgs {
 // window along y and LDS rings along x; variant 2: the same with the next
 // row's loads issued before the current row is computed.  variant 1 (3D):
 // plane sweeps of a column tile (32x16, 64x8 or 16x16 for bx = 32, 64, 16)
-// over `rows` planes with a register window along z and LDS plane rings.
+// over `rows` planes with a register window along z and LDS plane rings;
+// variant 2 (3D): the same with every load of the next plane issued during
+// the current one; variant 3 (3D): only the staged planes and the z window
+// one plane ahead, the point's own values at the top of their plane.
 struct KernelConfig {
     int variant;
     int bx;
     int rows;
+    int by = 0;              // 3D: tile rows in y (0: the default of bx)
 };
 
 // Many 2D domains advanced by one launch per phase (batched serving).  The

@@ -660,7 +660,11 @@ __device__ __forceinline__ void stage_store(float *dst, const Staged<W, H, NT> &
     }
 }
 
-template <int L, bool CENTRED, int BX, int BY, bool PP, bool PF>
+// PF: 0 -- every plane's loads issued in its own iteration; 1 -- all loads
+// of plane k + 1 issued during plane k; 2 -- only the staged planes and the
+// z window one plane ahead, the point's own values (medium, memory
+// variables) issued at the top of their own plane (fewer registers).
+template <int L, bool CENTRED, int BX, int BY, bool PP, int PF>
 __global__ void __launch_bounds__(BX *BY) pressure_sweep3d(const StepArgs a, int rows, int nbx, int nby, int nblocks)
 {
     constexpr int NT = BX * BY;
@@ -705,8 +709,8 @@ __global__ void __launch_bounds__(BX *BY) pressure_sweep3d(const StepArgs a, int
         int l;
         float m[3][L];
     };
-    auto load_own = [&](Own &o, int k) {
-        o.vzn = ldz3(vz, g, i, j, k + 3);
+    auto load_zwin = [&](Own &o, int k) { o.vzn = ldz3(vz, g, i, j, k + 3); };
+    auto load_point = [&](Own &o, int k) {
         o.p0 = 0.0f;
         o.k0 = 1.0f;
         o.q0 = 0.0f;
@@ -725,6 +729,10 @@ __global__ void __launch_bounds__(BX *BY) pressure_sweep3d(const StepArgs a, int
                     o.m[ax][nu] = ntld(at_plane(plane_base(a.psi2 + (int64_t)(ax * L + nu) * g.stride, g, k), pt));
         }
     };
+    auto load_own = [&](Own &o, int k) {
+        load_zwin(o, k);
+        load_point(o, k);
+    };
     Staged<XW, XH, NT> px;
     Staged<YW, YH, NT> py;
     Staged<ZW, ZH, NT> pz;
@@ -733,7 +741,10 @@ __global__ void __launch_bounds__(BX *BY) pressure_sweep3d(const StepArgs a, int
         stage_load<XW, XH, NT>(px, vx, g, x0 - 4, y0 - 1, z0 + 1, tid);
         stage_load<YW, YH, NT>(py, vy, g, x0 - 1, y0 - 4, z0 + 1, tid);
         stage_load<ZW, ZH, NT>(pz, vz, g, x0 - 1, y0 - 1, z0, tid);
-        load_own(cur, z0);
+        if (PF == 1)
+            load_own(cur, z0);
+        else
+            load_zwin(cur, z0);
     }
     for (int k = z0; k < zend; ++k) {
         if (PF) {
@@ -746,12 +757,16 @@ __global__ void __launch_bounds__(BX *BY) pressure_sweep3d(const StepArgs a, int
             stage<ZW, ZH, NT>(sz[k % 3], vz, g, x0 - 1, y0 - 1, k, tid);
             load_own(cur, k);
         }
-        const Own o = cur;
+        Own o = cur;
+        if (PF == 2) load_point(o, k);
         if (PF && k + 1 < zend) {               // next plane's loads in flight during this one
             stage_load<XW, XH, NT>(px, vx, g, x0 - 4, y0 - 1, k + 2, tid);
             stage_load<YW, YH, NT>(py, vy, g, x0 - 1, y0 - 4, k + 2, tid);
             stage_load<ZW, ZH, NT>(pz, vz, g, x0 - 1, y0 - 1, k + 1, tid);
-            load_own(cur, k + 1);
+            if (PF == 1)
+                load_own(cur, k + 1);
+            else
+                load_zwin(cur, k + 1);
         }
         const float p0 = o.p0, k0 = o.k0, q0 = o.q0, r0 = o.r0;
         const int l = o.l;
@@ -818,7 +833,7 @@ __global__ void __launch_bounds__(BX *BY) pressure_sweep3d(const StepArgs a, int
     }
 }
 
-template <int L, bool CENTRED, int BX, int BY, bool PP, bool PF>
+template <int L, bool CENTRED, int BX, int BY, bool PP, int PF>
 __global__ void __launch_bounds__(BX *BY) velocity_sweep3d(const StepArgs a, int rows, int nbx, int nby, int nblocks)
 {
     // with receivers, block 0 records them and blocks 1.. take the tiles
@@ -863,8 +878,8 @@ __global__ void __launch_bounds__(BX *BY) velocity_sweep3d(const StepArgs a, int
         int l;
         float m[3][L];
     };
-    auto load_own = [&](Own &o, int k) {
-        o.pn = ldz3(pp, g, i, j, k + 4);
+    auto load_zwin = [&](Own &o, int k) { o.pn = ldz3(pp, g, i, j, k + 4); };
+    auto load_point = [&](Own &o, int k) {
         o.u[0] = o.u[1] = o.u[2] = 0.0f;
         o.l = 0;
         if (live && k < nz) {
@@ -878,6 +893,10 @@ __global__ void __launch_bounds__(BX *BY) velocity_sweep3d(const StepArgs a, int
                     o.m[ax][nu] = ntld(at_plane(plane_base(a.psi1 + (int64_t)(ax * L + nu) * g.stride, g, k), pt));
         }
     };
+    auto load_own = [&](Own &o, int k) {
+        load_zwin(o, k);
+        load_point(o, k);
+    };
     Staged<PW, PH, NT> ps;
     Staged<RW, RH, NT> rs, ks;
     Own cur;
@@ -885,7 +904,10 @@ __global__ void __launch_bounds__(BX *BY) velocity_sweep3d(const StepArgs a, int
         stage_load<PW, PH, NT>(ps, pp, g, x0 - 4, y0 - 4, z0 + 1, tid);
         stage_load<RW, RH, NT>(rs, a.rho, g, x0, y0, z0 + 1, tid);
         stage_load<RW, RH, NT>(ks, a.kap, g, x0, y0, z0 + 1, tid);
-        load_own(cur, z0);
+        if (PF == 1)
+            load_own(cur, z0);
+        else
+            load_zwin(cur, z0);
     }
     for (int k = z0; k < zend; ++k) {
         if (PF) {
@@ -898,12 +920,16 @@ __global__ void __launch_bounds__(BX *BY) velocity_sweep3d(const StepArgs a, int
             stage<RW, RH, NT>(sk[(k + 1) % 3], a.kap, g, x0, y0, k + 1, tid);
             load_own(cur, k);
         }
-        const Own o = cur;
+        Own o = cur;
+        if (PF == 2) load_point(o, k);
         if (PF && k + 1 < zend) {
             stage_load<PW, PH, NT>(ps, pp, g, x0 - 4, y0 - 4, k + 2, tid);
             stage_load<RW, RH, NT>(rs, a.rho, g, x0, y0, k + 2, tid);
             stage_load<RW, RH, NT>(ks, a.kap, g, x0, y0, k + 2, tid);
-            load_own(cur, k + 1);
+            if (PF == 1)
+                load_own(cur, k + 1);
+            else
+                load_zwin(cur, k + 1);
         }
         const float u[3] = {o.u[0], o.u[1], o.u[2]};
         const int l = o.l;
@@ -1004,12 +1030,14 @@ hipError_t launch_sweep(const StepArgs &a, bool pressure, const KernelConfig &kc
     return hipErrorInvalidValue;
 }
 
-template <int L, bool C, bool PP, bool PF>
+template <int L, bool C, bool PP, int PF>
 hipError_t launch_sweep3(const StepArgs &a, bool pressure, const KernelConfig &kc, hipStream_t st)
 {
-#define FW2_SWEEP3(BXV, BYV)                                                                            \
-    if constexpr (L <= 4 || (BXV == 64 && BYV == 8))                                                    \
-    if (kc.bx == BXV) {                                                                                 \
+    // tile BX x BY: kc.bx selects 16 x 16, 32 x 16 or 64 x 8 (kc.by = 0), or
+    // with kc.by the 256-thread tiles 64 x 4 and 32 x 8 (variant 3 only)
+#define FW2_SWEEP3(BXV, BYV, COND)                                                                      \
+    if constexpr (COND)                                                                                 \
+    if (kc.bx == BXV && (kc.by == 0 ? (BYV == (BXV == 64 ? 8 : 16)) : kc.by == BYV)) {                  \
         const int nbx = (a.geo.n[0] + BXV - 1) / BXV, nby = (a.geo.n[1] + BYV - 1) / BYV;                \
         const int nbz = (a.geo.n[2] + kc.rows - 1) / kc.rows;                                           \
         const int nblocks = nbx * nby * nbz;                                                            \
@@ -1022,9 +1050,11 @@ hipError_t launch_sweep3(const StepArgs &a, bool pressure, const KernelConfig &k
                                a, kc.rows, nbx, nby, nblocks);                                          \
         return hipGetLastError();                                                                       \
     }
-    FW2_SWEEP3(32, 16)
-    FW2_SWEEP3(64, 8)
-    FW2_SWEEP3(16, 16)
+    FW2_SWEEP3(32, 16, L <= 4)
+    FW2_SWEEP3(64, 8, true)
+    FW2_SWEEP3(16, 16, L <= 4)
+    FW2_SWEEP3(64, 4, L <= 4 && PF == 2)
+    FW2_SWEEP3(32, 8, L <= 4 && PF == 2)
 #undef FW2_SWEEP3
     return hipErrorInvalidValue;
 }
@@ -1143,10 +1173,11 @@ hipError_t dispatch_variant(const StepArgs &a, const KernelConfig &kc, hipStream
         // the registers)
         if (kc.variant == 0) return P ? launch_p<NDIM, L, C, PP>(a, st) : launch_v<NDIM, L, C, PP>(a, st);
         if (NDIM == 2) return launch_sweep<L, C, false, PP>(a, P, KernelConfig{1, 256, kc.rows}, st);
-        return launch_sweep3<L, C, PP, false>(a, P, KernelConfig{1, 64, kc.rows}, st);
+        return launch_sweep3<L, C, PP, 0>(a, P, KernelConfig{1, 64, kc.rows}, st);
     } else {
-        if (NDIM == 3 && kc.variant == 1) return launch_sweep3<L, C, PP, false>(a, P, kc, st);
-        if (NDIM == 3 && kc.variant == 2) return launch_sweep3<L, C, PP, true>(a, P, kc, st);
+        if (NDIM == 3 && kc.variant == 1) return launch_sweep3<L, C, PP, 0>(a, P, kc, st);
+        if (NDIM == 3 && kc.variant == 2) return launch_sweep3<L, C, PP, 1>(a, P, kc, st);
+        if (NDIM == 3 && kc.variant == 3) return launch_sweep3<L, C, PP, 2>(a, P, kc, st);
         if (NDIM == 2 && kc.variant == 1) return launch_sweep<L, C, false, PP>(a, P, kc, st);
         if (NDIM == 2 && kc.variant == 2) return launch_sweep<L, C, true, PP>(a, P, kc, st);
         return P ? launch_p<NDIM, L, C, PP>(a, st) : launch_v<NDIM, L, C, PP>(a, st);

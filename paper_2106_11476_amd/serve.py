@@ -106,9 +106,12 @@ class Server:
     fields in the device's last-level cache between the two phases of a step
     (a batched phase sweeps every domain before the next phase starts), so
     such requests are stepped alone with the single-domain kernels, one at a
-    time in arrival order, on the same stream after the batched launch; the
-    others wait resident, with their setup and read-back still overlapping
-    the device work.
+    time in arrival order; the others wait resident, with their setup and
+    read-back still overlapping the device work.  The device serves the
+    oldest work first: in each chunk it runs either the batch (when its oldest
+    request arrived before the next solo request) or that solo request, not
+    both, so neither waits behind a chunk of the other that has just started
+    and large requests complete in arrival order as they would one at a time.
     """
 
     def __init__(self, budget_bytes, max_active=32, chunk=64, device="cuda:0", tile=(256, 4),
@@ -216,16 +219,19 @@ class Server:
                 continue
             stats.peak_bytes = max(stats.peak_bytes, sum(r.footprint for r, _ in active + solo))
             stats.peak_active = max(stats.peak_active, len(active) + len(solo))
-            # run until the next event: the first completion among the batched
-            # requests and the solo request in turn, or (when requests wait to
-            # join) the next chunk boundary
-            left = [r.n_steps - d.current_step() for r, d in active + solo[:1]]
+            # oldest work first: the batch if its oldest request arrived before
+            # the solo request in turn, else that solo request
+            run_batch = bool(active) and (not solo or min((r.arrival, r.rid) for r, _ in active)
+                                          <= (solo[0][0].arrival, solo[0][0].rid))
+            # run until the next event: the first completion of the work in
+            # turn, or (when requests wait to join) the next chunk boundary
+            left = [r.n_steps - d.current_step() for r, d in (active if run_batch else solo[:1])]
             to_done = min(left)
             waiting = pending or (queue and len(active) + len(solo) < self.max_active)
             k = max(int(min(to_done, self.chunk) if waiting else to_done), 1)
-            if active:
+            if run_batch:
                 self.batch.step(k)
-            if solo:
+            else:
                 r, d = solo[0]
                 d.step(min(k, r.n_steps - d.current_step()))
             stats.chunks += 1

@@ -152,3 +152,50 @@ def test_slab_run_equals_the_whole_grid_run_and_the_oracle(case, monkeypatch):
     if config is None:
         ref, rtr = oracle_run(prob, steps)
         compare(g, tg, ref, rtr, label, prob=prob)
+
+
+@pytest.mark.parametrize("shape,L", [((70, 45), 3), ((26, 21, 19), 2)])
+def test_zero_halos_stay_zero_after_stepping(shape, L):
+    """Outside the grid every field is zero (the stencils read the halo cells
+    instead of testing bounds): after steps from a random state with sources
+    and receivers, every halo cell of p, v and the memory variables in the
+    state block is still exactly zero, and so is the v sample past the last
+    pressure sample along its axis."""
+    torch = _torch()
+    from paper_2106_11476_amd import fw2
+    prob = W.random_medium(shape, L, 3, seed=13, nb=5, ntr=3)
+    nd = len(shape)
+    mid = [s // 2 for s in shape]
+    prob.src_idx = prob.flat(*[np.array([m]) for m in mid])
+    prob.src_sig = np.zeros(1, np.int32)
+    prob.src_w = np.ones(1, np.float32)
+    prob.signals = W.gaussian_pulse(60, prob.dt, 3e6, 3, 1e5)[None]
+    prob.rcv_idx = prob.flat(*[np.array([m + 1]) for m in mid])
+    _say("zero halos after stepping", shape, "L", L)
+    dom = fw2.from_problem(prob, device="cuda:0", cap_steps=40)
+    dom.write_fields(_state(prob, 9))
+    dom.step(40)
+    buf = dom.new_state_buffer()
+    dom.save_state(buf)
+    torch.cuda.synchronize()
+    f = dom.read_fields(fw2.FIELD_V)
+    dom.destroy_domain()
+    buf = buf.cpu().numpy()
+    n3 = list(shape) + [1] * (3 - nd)
+    nx, ny, nz = n3
+    pitch = ((nx + 8 + 63) // 64) * 64
+    planes = nz + 8 if nd == 3 else 1
+    stride = pitch * (ny + 8) * planes
+    n_arr = 1 + nd + 2 * nd * L
+    assert buf.size == n_arr * stride
+    for k in range(n_arr):
+        a = buf[k * stride:(k + 1) * stride].reshape(planes, ny + 8, pitch)
+        win = ((slice(4, 4 + nz) if nd == 3 else slice(0, 1)), slice(4, 4 + ny), slice(4, 4 + nx))
+        assert a[win].any(), k
+        halo = np.ones(a.shape, bool)
+        halo[win] = False
+        assert not a[halo].any(), ("halo cell written", k)
+    for a in range(nd):                            # the v sample past the grid along its axis
+        sl = [slice(None)] * nd
+        sl[nd - 1 - a] = -1
+        assert not f["v"][a][tuple(sl)].any(), a
