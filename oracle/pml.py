@@ -24,7 +24,11 @@ and the workloads use reading A):
 * reading "A_kappa": reading A with the target of each derivative scaled by
   its own kappa (d~_i = kappa_i d~), which keeps the ratio of the two
   stretch factors, and so the impedance, at the interior's value deep in the
-  layer when kappa_1 != kappa_2.
+  layer when kappa_1 != kappa_2;
+* reading "A_alpha_tr": reading A with alpha^{nu=1} taken linearly to 0 over
+  the inner L_Tr instead of the whole L_CPML (a tissue alpha far above the
+  angular frequency otherwise turns the nu = 1 damping into a real stretch
+  over most of the layer).
 """
 import numpy as np
 
@@ -88,11 +92,15 @@ def profile(s_cells, h, nb, ntr, d0, a0, nu, c_p, R_c, N, reading="A", kappa=1.0
             Lb = (nb - ntr) * h
             x = np.maximum(s - ntr, 0.0) * h
             return blend(d0, dt_, g_polynomial(x, Lb, N)), blend(a0, 0.0, g_linear(x, Lb))
-        if reading not in ("A", "A_kappa", "B"):
+        if reading not in ("A", "A_kappa", "B", "A_alpha_tr"):
             raise ValueError("unknown boundary reading %r" % (reading,))
         x = s * h
         d = blend(d0, dt_, g_polynomial(x, L, N))
-        a = blend(a0, 0.0, g_linear(x, L))
+        if reading == "A_alpha_tr" and ntr > 0:
+            Ltr = ntr * h
+            a = blend(a0, 0.0, g_linear(np.minimum(x, Ltr), Ltr))
+        else:
+            a = blend(a0, 0.0, g_linear(x, L))
         return d, a
     # nu >= 2: cosine ramp over the transition layer, zero past it.
     if ntr == 0:
