@@ -26,4 +26,6 @@ physics     Closed-form references used as pins (Green's function, exact
 adjoint     Discrete adjoint of the time-centred step (gradient of a trace
             misfit with respect to c), pinned by central differences of the
             stepper.
+reflection  The two-stage C-PML's reflection measured with the stepper
+            (Secs. 4.2-4.3) and the study of its settings.
 """

@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from oracle import physics, relaxation, solver
+from oracle import physics, reflection, relaxation, solver
 
 C0 = 1540.0
 
@@ -147,66 +147,63 @@ def test_printed_recursion_loses_attenuation(oracle_lib):
 
 # ----------------------------------------------------- C-PML reflection (E2/E3) ---
 
-def _reflection_db(row, L, angles, ppw=16, cfl=0.2, ntr_l=3, nbd_l=1, D_l=1.0, f0=2e6, ext_l=20,
-                   margin_l=2):
-    """Reflection of the bottom two-stage layer at the given incidence
-    angles: run A has the layer D_l wavelengths below a point source; run B
-    is identical but ext_l wavelengths deeper (no reflection in the window).
-    R = max|p_A - p_B| at a receiver at the source depth, offset 2 D tan(theta),
-    over the direct-wave peak at the image distance 2 D / cos(theta)."""
-    lam = ppw
-    nb, ntr = (ntr_l + nbd_l) * lam, ntr_l * lam
-    D = int(round(D_l * lam))
-    offs = [int(round(2 * D * np.tan(np.radians(a)))) for a in angles]
-    rimg = [2 * D / np.cos(np.radians(a)) for a in angles]
-    half = max(max(offs), int(max(rimg))) + margin_l * lam
-    nx = 2 * half + 2 * nb + 1
-    top = margin_l * lam
-    ny_a = nb + top + D + nb
-    res = {}
-    for name, ny in (("A", ny_a), ("B", ny_a + ext_l * lam)):
-        prob = W.homogeneous((nx, ny), L=L, row=row, nb=(nb, nb), ntr=(ntr, ntr), f0=f0, ppw=ppw, cfl=cfl)
-        h, dt = prob.h, prob.dt
-        sx, sy = nx // 2, nb + top
-        npulse = W.pulse_length(dt, f0, 3)
-        nt = int((max(rimg) + 4 * lam) * h / C0 / dt) + npulse
-        prob.src_idx = prob.flat(np.array([sx]), np.array([sy]))
-        prob.src_sig = np.zeros(1, np.int32)
-        prob.src_w = np.ones(1, np.float32)
-        prob.signals = W.gaussian_pulse(npulse, dt, f0, 3, 1.0)[None]
-        rx = np.array([sx + o for o in offs] + [sx - int(round(r)) for r in rimg])
-        prob.rcv_idx = prob.flat(rx, np.full(rx.size, sy))
-        _, res[name] = solver.run(prob, nt)
-    A, B = res["A"], res["B"]
-    n = len(angles)
-    return np.array([20 * np.log10(np.abs(A[:, k] - B[:, k]).max() / np.abs(B[:, n + k]).max())
-                     for k in range(n)])
+_reflection_db = reflection.reflection_db
 
 
-def test_cpml_reflection_special_case_and_fitted_tissue(oracle_lib):
-    """Secs. 4.2-4.3 at 16 ppw, CFL 0.2, 3 lambda transition + 1 lambda
-    bound: the C-PML special case (lossless interior) reflects below -60 dB at
-    normal incidence and below -49 dB up to 60 degrees; with the fitted
-    two-mechanism tissue the two-stage layer stays below -49 dB at normal
-    incidence, and a 5 + 1 lambda layer is better than 3 + 1."""
-    r = _reflection_db(W.lossless_row(1), 1, (0, 30, 45, 60))
-    assert r[0] < -60, r
-    assert np.all(r < -49), r
+ANGLES = (0, 20, 45, 60, 70, 80)
+
+
+def test_cpml_reflection_over_the_stated_angles(oracle_lib, golden):
+    """Secs. 4.2-4.3 at 16 ppw, CFL 0.2, 3 lambda transition + 1 lambda bound:
+    the stated bound of about -49 dB from 0 to 80 degrees and the -50 dB of
+    the 3 + 1 lambda layer, read from the fixture.  R_c is not stated: with
+    R_c = 1e-4 the C-PML special case (lossless interior) meets the bound at
+    every angle; with the library's R_c = 1e-3 the fitted two-mechanism
+    tissue meets it up to 60 degrees, and above that reflects more (recorded
+    finding: -46.6 dB at 70, -34.6 dB at 80 degrees).  In this measurement
+    (point source one wavelength above the layer) the reflection grows with
+    the angle: the minimum near 45 degrees of the paper's figure is not
+    reproduced (recorded finding)."""
+    st = golden.stated()
+    bound, b31 = st["reflection_db_all_angles_max"], st["reflection_db_tr3_bd1"]
+    assert (st["ppw_reflection"], st["cfl_reflection"]) == (16, 0.2)
+    r = _reflection_db(W.lossless_row(1), 1, ANGLES, pml_Rc=1e-4)
+    assert np.all(r <= bound), r
+    assert r[0] <= b31, r
     row = W.tissue_row(0.5, 1.0, 2, 2e6)
-    r31 = _reflection_db(row, 2, (0,))[0]
-    assert r31 < -49, r31
-    r51 = _reflection_db(row, 2, (0,), ntr_l=5)[0]
-    assert r51 < r31, (r31, r51)
+    rf = _reflection_db(row, 2, ANGLES)
+    assert rf[0] <= b31, rf
+    assert np.all(rf[:4] <= bound), rf                       # 0 .. 60 degrees
+    assert -49.0 < rf[4] < -44.0 and -38.0 < rf[5] < -31.0, rf   # 70, 80 degrees: above the bound
+    for curve in (r, rf):                                     # grows with the angle: no minimum at 45
+        assert np.all(np.diff(curve) > 0), curve
 
 
-def test_cpml_reflection_table2_tissue_recorded(oracle_lib):
-    """With Table 2 verbatim (kappa1 = 0.835, kappa2 = 1.19 and very fast
-    nabla_1 mechanisms) the layer's stretch ratio moves from the tissue's
-    towards 1, so the impedance changes inside the layer: measured about
-    -38 dB at normal incidence (recorded finding; the paper's -49 dB is
-    reached by the special case and the fitted tissue above)."""
-    r = _reflection_db(W.TABLE2_ROW, 2, (0,))[0]
-    assert -45 < r < -30, r
+def test_cpml_reflection_thickness_and_table2(oracle_lib, golden):
+    """Sec. 4.2: about -50 dB with a 3 + 1 lambda layer and -60 dB with
+    5 + 1 lambda, read from the fixture, at normal incidence.  The lossless
+    special case meets the 5 + 1 figure with the library's R_c = 1e-3 (and
+    the 3 + 1 figure, checked over the angles above).  Table 2 verbatim
+    does not (recorded finding: about -38.7 dB at 3 + 1): its nu = 1 nabla_1
+    mechanism has alpha = 2.83e8 1/s, twenty times the angular frequency of
+    the 2 MHz pulse, and with alpha ramped linearly to 0 over the whole layer
+    (Table 1) the damping d / (alpha + i omega) of that derivative is nearly
+    real over most of the layer, so the layer absorbs only part of what R_c
+    promises.  Two checks of that reading of the finding: the reflection
+    follows R_c at about 10 dB per decade (with R_c = 1e-5 Table 2 meets both
+    stated figures), and taking alpha to 0 over the transition layer instead
+    (oracle reading "A_alpha_tr", a study reading, not the library's) brings
+    Table 2 below -50 dB at R_c = 1e-3."""
+    st = golden.stated()
+    b31, b51 = st["reflection_db_tr3_bd1"], st["reflection_db_tr5_bd1"]
+    assert _reflection_db(W.lossless_row(1), 1, (0,), ntr_l=5)[0] <= b51
+    t3 = _reflection_db(W.TABLE2_ROW, 2, (0,))[0]
+    assert -42.0 < t3 < -35.0, t3
+    t3e = _reflection_db(W.TABLE2_ROW, 2, (0,), pml_Rc=1e-5)[0]
+    assert t3e <= b31 and -24.0 < t3e - t3 < -17.0, (t3, t3e)
+    assert _reflection_db(W.TABLE2_ROW, 2, (0,), ntr_l=5, pml_Rc=1e-5)[0] <= b51
+    ta = _reflection_db(W.TABLE2_ROW, 2, (0,), pml_reading="A_alpha_tr")[0]
+    assert ta <= b31 and ta < t3 - 10.0, (t3, ta)
 
 
 # ------------------------------------------------ nonlinear steepening (E5) ---
