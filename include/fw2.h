@@ -222,9 +222,33 @@ fw2_status fw2_check_finite(fw2_domain *dom, float limit);
  * a caller-owned device buffer and fw2_load_state copies one back and sets
  * the step counter (both asynchronous on the domain's stream): checkpoints.
  *
- * The discrete adjoint (the paper's extension to full waveform inversion:
- * the relaxation is not time-reversible, so its adjoint is derived
- * explicitly) gives the gradient of J = 1/2 sum_k sum_r (trace[k][r] -
+ * fw2_step_into advances n steps out of place through caller-owned state
+ * blocks, for recomputing the forward states between two checkpoints (the
+ * checkpointed recomputation of the adjoint below; library infrastructure):
+ * step i (i = 0..n-1) reads block i-1 (dev_first for i = 0) and writes block
+ * i of dev_states (n consecutive blocks of fw2_state_bytes), i.e. block i
+ * holds the state after step s + i + 1 when dev_first holds the state at the
+ * domain's current step s.  Sources are added and receivers recorded as in
+ * fw2_step, and the step counter advances by n; the domain's own fields are
+ * neither read nor written (they stay at step s: fw2_load_state before
+ * stepping the domain itself again).  Only cells inside the grid are written,
+ * so the cells outside it (the halo, and the last sample of each velocity
+ * component and its psi1 along that component's axis) must hold zero in
+ * every destination block, as in a zero-filled buffer or a block written by
+ * fw2_save_state; they then stay zero.  Blocks need 4-byte alignment; at
+ * 240 bytes past a 256-byte boundary (where the domain's own block starts)
+ * every row starts on a cache line.  dev_first must not overlap the
+ * destination blocks.
+ * n = 0 does nothing (the pointers may then be NULL).
+ * Asynchronous on the domain's stream; the n steps are captured in a HIP
+ * graph (reused while dev_first, dev_states and n stay the same) unless
+ * graphs are off (fw2_set_graph_chunk 0) or kernel timing is on.  Slabs:
+ * FW2_E_UNSUPPORTED.
+ *
+ * The discrete adjoint (the paper's extension to full waveform inversion,
+ * Sec. 5: the memory-variable recursion is dissipative, so the reverse step
+ * is the transpose of the linearised forward step, not the scheme run
+ * backwards) gives the gradient of J = 1/2 sum_k sum_r (trace[k][r] -
  * obs[k][r])^2 with respect to the sound-speed map.  It is the exact
  * transpose of the time-centred scheme's step (FW2_RELAX_CENTRED only;
  * FW2_E_UNSUPPORTED otherwise), linearised about the forward state; c enters
@@ -245,6 +269,7 @@ fw2_status fw2_check_finite(fw2_domain *dom, float limit);
 fw2_status fw2_state_bytes(const fw2_domain *dom, uint64_t *bytes);
 fw2_status fw2_save_state(fw2_domain *dom, void *dev_dst);
 fw2_status fw2_load_state(fw2_domain *dom, const void *dev_src, int64_t step);
+fw2_status fw2_step_into(fw2_domain *dom, int32_t n, const void *dev_first, void *dev_states);
 fw2_status fw2_adjoint_workspace_bytes(const fw2_domain *dom, uint64_t *bytes);
 fw2_status fw2_adjoint_begin(fw2_domain *dom, void *dev_workspace, uint64_t workspace_bytes);
 fw2_status fw2_adjoint_step(fw2_domain *dom, const void *dev_state, const void *dev_state_prev, int64_t step,

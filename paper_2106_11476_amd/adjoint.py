@@ -17,7 +17,9 @@ torch.autograd.Function:
             residual rows as the adjoint sources, and returns dJ/dc.
 
 Memory: ceil(n / K) checkpoint blocks plus K recompute blocks; the default
-K = ceil(sqrt(n)) balances the two (one extra forward pass in total).
+K = ceil(sqrt(n)) balances the two (one extra forward pass in total).  The
+recompute steps out of place into the segment's blocks (fw2_step_into), so no
+state is copied per step, and replays one HIP graph per segment.
 """
 import math
 
@@ -84,15 +86,18 @@ def _misfit_function():
             dom, ckpts, K, n = ctx.dom, ctx.ckpts, ctx.K, ctx.n
             res = None if ctx.residual is None else (ctx.residual * gJ.to(torch.float32)).contiguous()
             dom.adjoint_begin()
+            # seg[k] holds the state at step n0 + k: the segment's checkpoint
+            # copied into seg[0], the others recomputed from it out of place
+            # (fixed buffers, so every full segment replays one HIP graph)
             seg = dom.new_state_buffer(K)
             for s in reversed(range(ckpts.shape[0])):
                 n0 = s * K
                 m = min(K, n - n0)
-                dom.load_state(ckpts[s], n0)
-                for i in range(m):
-                    dom.save_state(seg[i])
-                    if i + 1 < m:
-                        dom.step(1)
+                with torch.cuda.stream(dom.stream):
+                    seg[0].copy_(ckpts[s])
+                if m > 1:
+                    dom.set_current_step(n0)
+                    dom.step_into(m - 1, seg[0], seg[1:])
                 for k in reversed(range(m)):
                     dom.adjoint_step(seg[k], n0 + k, None if res is None else res[n0 + k],
                                      prev=seg[k - 1] if k > 0 else None)

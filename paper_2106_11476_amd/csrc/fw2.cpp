@@ -211,6 +211,10 @@ struct fw2_domain {
     fw2::AdjointBuffers adj;
     int64_t adj_pp_step = -1;        // step whose p'' and S the adjoint buffers hold
     bool mid_step = false;           // fw2_step_phase ran the pressure phase of a step
+    hipGraphExec_t into_graph = nullptr;   // fw2_step_into's last capture and its arguments
+    const void *into_first = nullptr;
+    void *into_states = nullptr;
+    int32_t into_n = 0;
     int64_t npts() const { return (int64_t)ly.geo.n[0] * ly.geo.n[1] * ly.geo.n[2]; }
 };
 
@@ -229,6 +233,10 @@ void drop_graph(fw2_domain *d)
     if (d->graph) {
         (void)hipGraphExecDestroy(d->graph);
         d->graph = nullptr;
+    }
+    if (d->into_graph) {
+        (void)hipGraphExecDestroy(d->into_graph);
+        d->into_graph = nullptr;
     }
 }
 
@@ -476,6 +484,7 @@ fw2_status fw2_create_domain(const fw2_domain_desc *desc, void *dev_workspace, u
     a.v = fb + g.stride;
     a.psi1 = fb + (1 + nd) * g.stride;
     a.psi2 = a.psi1 + (int64_t)nd * L * g.stride;
+    a.out = 0;                                       // in place
     float *kap = a.psi2 + (int64_t)nd * L * g.stride;
     float *nlq = kap + g.stride;
     float *rho = nlq + g.stride;
@@ -858,6 +867,96 @@ fw2_status fw2_load_state(fw2_domain *d, const void *dev_src, int64_t step)
     FW2_HIP(hipMemcpyAsync(d->args.p, dev_src, (size_t)state_floats(d) * 4, hipMemcpyDeviceToDevice, d->stream));
     FW2_HIP(fw2::launch_set_counter(d->counter, step, d->stream));
     d->step = step;
+    return FW2_OK;
+}
+
+namespace {
+
+// One step out of place: the state block at src (the domain's field layout)
+// to the block at dst.  The pressure phase reads p, v, psi2 of src and writes
+// p, psi2 of dst; the sources add into dst's p; the velocity phase reads that
+// p and v, psi1 of src and writes v, psi1 of dst.
+fw2_status enqueue_step_into(fw2_domain *d, const float *src, float *dst, hipStream_t s)
+{
+    const int L = d->desc.n_relax, sch = d->desc.relax_scheme, nd = d->desc.ndim;
+    const int64_t S = d->ly.geo.stride;
+    fw2::StepArgs a = d->args;
+    a.p = const_cast<float *>(src);
+    a.v = a.p + S;
+    a.psi1 = a.p + (int64_t)(1 + nd) * S;
+    a.psi2 = a.psi1 + (int64_t)nd * L * S;
+    a.out = dst - src;
+    FW2_HIP(fw2::launch_pressure(a, L, sch, d->kc, s));
+    fw2::SparseArgs src_pts = d->src, rcv = d->rcv;
+    src_pts.p = dst;
+    rcv.p = dst;
+    a.p = dst;
+    a.rcv.p = dst;
+    FW2_HIP(fw2::launch_sources(src_pts, s));
+    if (!a.rcv.step) FW2_HIP(fw2::launch_receivers(rcv, s));
+    FW2_HIP(fw2::launch_velocity(a, L, sch, d->kc, s));
+    return FW2_OK;
+}
+
+fw2_status enqueue_steps_into(fw2_domain *d, int32_t n, const float *first, float *states, hipStream_t s)
+{
+    const int64_t B = state_floats(d);
+    for (int32_t i = 0; i < n; ++i) {
+        fw2_status st = enqueue_step_into(d, i == 0 ? first : states + (int64_t)(i - 1) * B, states + (int64_t)i * B, s);
+        if (st != FW2_OK) return st;
+    }
+    return FW2_OK;
+}
+
+}  // namespace
+
+fw2_status fw2_step_into(fw2_domain *d, int32_t n, const void *dev_first, void *dev_states)
+{
+    if (!d) return fail(FW2_E_STATE, "domain is NULL");
+    if (n < 0) return fail(FW2_E_INVALID, "n < 0");
+    if (d->mid_step) return fail(FW2_E_STATE, "a step is half done (fw2_step_phase): run its velocity phase first");
+    if (d->desc.slab_nz > 0) return fail(FW2_E_UNSUPPORTED, "slabs exchange halos between phases: use fw2_step_phase");
+    if (n == 0) return FW2_OK;
+    if (!dev_first || !dev_states) return fail(FW2_E_INVALID, "first or states is NULL");
+    if ((uintptr_t)dev_first % 4 || (uintptr_t)dev_states % 4) return fail(FW2_E_INVALID, "blocks must be 4-byte aligned");
+    const uint64_t bytes = (uint64_t)state_floats(d) * 4;
+    const uintptr_t f0 = (uintptr_t)dev_first, s0 = (uintptr_t)dev_states, s1 = s0 + (uint64_t)n * bytes;
+    if (f0 + bytes > s0 && f0 < s1) return fail(FW2_E_INVALID, "first overlaps the destination blocks");
+    const float *first = (const float *)dev_first;
+    float *states = (float *)dev_states;
+    if (d->timing || d->graph_chunk <= 0 || n < 2) {
+        fw2_status st = enqueue_steps_into(d, n, first, states, d->stream);
+        if (st != FW2_OK) return st;
+        d->step += n;
+        return FW2_OK;
+    }
+    if (!d->into_graph || d->into_first != dev_first || d->into_states != dev_states || d->into_n != n) {
+        if (d->into_graph) {
+            (void)hipGraphExecDestroy(d->into_graph);
+            d->into_graph = nullptr;
+        }
+        if (!d->capture) FW2_HIP(hipStreamCreateWithFlags(&d->capture, hipStreamNonBlocking));
+        FW2_HIP(hipStreamBeginCapture(d->capture, hipStreamCaptureModeThreadLocal));
+        fw2_status st = enqueue_steps_into(d, n, first, states, d->capture);
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamEndCapture(d->capture, &graph);
+        if (st != FW2_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return st;
+        }
+        if (e != hipSuccess) return fail(FW2_E_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+        e = hipGraphInstantiate(&d->into_graph, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            d->into_graph = nullptr;
+            return fail(FW2_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+        }
+        d->into_first = dev_first;
+        d->into_states = dev_states;
+        d->into_n = n;
+    }
+    FW2_HIP(hipGraphLaunch(d->into_graph, d->stream));
+    d->step += n;
     return FW2_OK;
 }
 

@@ -52,6 +52,9 @@ struct StepArgs {
     float *v;                // v_a = v + a * stride
     float *psi1;             // psi1[a][nu] = psi1 + (a * L + nu) * stride
     float *psi2;
+    // Element offset from the fields a phase reads to those it writes: 0 steps
+    // in place; an out-of-place step reads one state block and writes the next.
+    int64_t out;
     const float *kap;        // kappa0 = 1 / (rho c^2)
     const float *nlq;        // kappa0 B, B = 1 - 2 beta as printed
     const float *rho;        // rho0

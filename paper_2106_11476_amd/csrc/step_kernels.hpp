@@ -124,13 +124,13 @@ __global__ void __launch_bounds__(kBX * kBY) pressure_kernel(const StepArgs a)
                 const float m = ntld(&ps[nu * g.stride]);
                 const float mn = fmaf(q.x, m, q.y * D);
                 Sa += CENTRED ? m : mn;
-                ntst(&ps[nu * g.stride], mn);
+                ntst(&ps[nu * g.stride + a.out], mn);
             }
             S += Sa;
         }
         const float pold = a.p[idx];
         const float kappa = a.kap[idx] * (1.0f + a.nlq[idx] * pold);
-        a.p[idx] = pold - a.dt * S / kappa;
+        a.p[idx + a.out] = pold - a.dt * S / kappa;
     }
 }
 
@@ -184,13 +184,13 @@ __global__ void __launch_bounds__(kBX * kBY) velocity_kernel(const StepArgs a)
                 const float m = ntld(&ps[nu * g.stride]);
                 const float mn = fmaf(q.x, m, q.y * D);
                 S += CENTRED ? m : mn;
-                ntst(&ps[nu * g.stride], mn);
+                ntst(&ps[nu * g.stride + a.out], mn);
             }
             const float pbar = 0.5f * (p0 + p1);
             const float rho_a = 0.5f * (r0 + a.rho[idx + o]);
             const float kap_a = 0.5f * (k0 + a.kap[idx + o]);
             float *va = a.v + ax * g.stride;
-            va[idx] = va[idx] - a.dt * S / (rho_a * (1.0f + (a.nlA * kap_a) * pbar));
+            va[idx + a.out] = va[idx] - a.dt * S / (rho_a * (1.0f + (a.nlA * kap_a) * pbar));
         }
     }
 }
@@ -324,8 +324,8 @@ __device__ __forceinline__ void pressure_tile2d(const StepArgs &a, int rows, int
     const bool live = i < nx;
     const float *__restrict__ vx = a.v;
     const float *__restrict__ vy = a.v + g.stride;
-    float *__restrict__ pp = a.p;
-    float *__restrict__ psi = a.psi2;
+    float *__restrict__ pp = a.p + a.out;        // written only
+    float *__restrict__ psi = a.psi2 + a.out;
 
     // prologue: window rows y0-4 .. y0+2, rings rows y0-1 and y0
     float w[8];
@@ -441,9 +441,9 @@ __device__ __forceinline__ void velocity_tile2d(const StepArgs &a, int rows, int
     const int nx = g.n[0], ny = g.n[1];
     const bool live = i < nx;
     const float *__restrict__ pp = a.p;
-    float *__restrict__ vx = a.v;
-    float *__restrict__ vy = a.v + g.stride;
-    float *__restrict__ psi = a.psi1;
+    float *__restrict__ vx = a.v + a.out;        // written only
+    float *__restrict__ vy = a.v + g.stride + a.out;
+    float *__restrict__ psi = a.psi1 + a.out;
 
     // prologue: window rows y0-3 .. y0+3; p ring rows y0-1, y0; rho/kappa row y0
     float w[8];
@@ -823,12 +823,12 @@ __global__ void __launch_bounds__(BX *BY) pressure_sweep3d(const StepArgs a, int
                 S += Sa;
             }
             const float kappa = k0 * (1.0f + q0 * p0);
-            *at_plane_w(plane_base(a.p, g, k), pt) = p0 - a.dt * S / kappa;
+            *at_plane_w(plane_base(a.p + a.out, g, k), pt) = p0 - a.dt * S / kappa;
 #pragma unroll
             for (int ax = 0; ax < 3; ++ax)
 #pragma unroll
                 for (int nu = 0; nu < L; ++nu)
-                    ntst(at_plane_w(plane_base(a.psi2 + (int64_t)(ax * L + nu) * g.stride, g, k), pt), m[ax][nu]);
+                    ntst(at_plane_w(plane_base(a.psi2 + a.out + (int64_t)(ax * L + nu) * g.stride, g, k), pt), m[ax][nu]);
         }
     }
 }
@@ -997,11 +997,11 @@ __global__ void __launch_bounds__(BX *BY) velocity_sweep3d(const StepArgs a, int
                     S += CENTRED ? m[ax][nu] : mn;
                     m[ax][nu] = mn;
                 }
-                *at_plane_w(plane_base(a.v + (int64_t)ax * g.stride, g, k), pt) =
+                *at_plane_w(plane_base(a.v + a.out + (int64_t)ax * g.stride, g, k), pt) =
                     u[ax] - a.dt * S / (rho_a * (1.0f + (a.nlA * kap_a) * pbar));
 #pragma unroll
                 for (int nu = 0; nu < L; ++nu)
-                    ntst(at_plane_w(plane_base(a.psi1 + (int64_t)(ax * L + nu) * g.stride, g, k), pt), m[ax][nu]);
+                    ntst(at_plane_w(plane_base(a.psi1 + a.out + (int64_t)(ax * L + nu) * g.stride, g, k), pt), m[ax][nu]);
             }
         }
     }

@@ -34,7 +34,7 @@ EXPORTS = ["fw2_workspace_bytes", "fw2_create_domain", "fw2_add_source", "fw2_ad
            "fw2_state_bytes", "fw2_save_state", "fw2_load_state", "fw2_adjoint_workspace_bytes",
            "fw2_adjoint_begin", "fw2_adjoint_step", "fw2_adjoint_gradient",
            "fw2_label_relaxation_map", "fw2_halo_bytes", "fw2_halo_pack", "fw2_halo_unpack",
-           "fw2_step_phase", "fw2_batch_create_noalloc"]
+           "fw2_step_phase", "fw2_batch_create_noalloc", "fw2_step_into"]
 
 
 class Fw2Error(RuntimeError):
@@ -92,6 +92,7 @@ def lib():
             "fw2_state_bytes": [vp, ctypes.POINTER(u64)],
             "fw2_save_state": [vp, vp],
             "fw2_load_state": [vp, vp, i64],
+            "fw2_step_into": [vp, i32, vp, vp],
             "fw2_adjoint_workspace_bytes": [vp, ctypes.POINTER(u64)],
             "fw2_adjoint_begin": [vp, vp, u64],
             "fw2_adjoint_step": [vp, vp, vp, i64, vp],
@@ -324,15 +325,30 @@ class Domain:
         return int(n.value)
 
     def new_state_buffer(self, count=None):
-        """Device buffer for one state block, or [count] blocks."""
-        shape = (self.state_bytes() // 4,) if count is None else (int(count), self.state_bytes() // 4)
-        return self.torch.empty(shape, dtype=self.torch.float32, device=self.device)
+        """Zero-filled device buffer for one state block, or [count] blocks.
+        Each block starts 240 bytes past a 256-byte boundary, as the domain's
+        own fields do, so that its rows sit on the same cache lines."""
+        B = self.state_bytes() // 4
+        n = 1 if count is None else int(count)
+        raw = self.torch.zeros(n * B + 64, dtype=self.torch.float32, device=self.device)
+        off = ((240 - raw.data_ptr() % 256) % 256) // 4
+        buf = raw[off:off + n * B]
+        return buf if count is None else buf.view(n, B)
 
     def save_state(self, dst):
         _check(lib().fw2_save_state(self._h, ctypes.c_void_p(dst.data_ptr())))
 
     def load_state(self, src, step):
         _check(lib().fw2_load_state(self._h, ctypes.c_void_p(src.data_ptr()), int(step)))
+
+    def step_into(self, n, first, states):
+        """n steps out of place from the state block `first` (at the current
+        step) into states[0..n-1] (zero-filled once, see new_state_buffer);
+        the domain's own fields are left as they are."""
+        if n > 0 and (states.dim() != 2 or states.shape[0] < n or states.shape[1] * 4 != self.state_bytes()):
+            raise ValueError("states must be [>= n, state_bytes / 4]")
+        _check(lib().fw2_step_into(self._h, int(n), ctypes.c_void_p(first.data_ptr()),
+                                   ctypes.c_void_p(states.data_ptr())))
 
     def adjoint_begin(self):
         n = ctypes.c_uint64(0)

@@ -7,7 +7,10 @@ workload at its stated step count and stores, in float32:
   p_dec     the final pressure on a decimated subgrid (every `stride`-th
             point along each axis, starting at 0)
   div_dec   the divergence sum_a D^-_a v_a of the final velocity at the same
-            points (the part of v that drives the pressure phase)
+            points
+  drive_dec the pressure increment of one more oracle step from the final
+            state at the same points: -dt S / K plus that step's sources,
+            S being what the pressure phase forms from v and psi2
   peak      max |p| over the final full-resolution field and the traces
 
 Workloads:
@@ -17,7 +20,8 @@ Workloads:
               (stride 4)
 
 The oracle needs hours on a few cores for each; --checkpoint-dir keeps the
-state every --every steps so that an interrupted run resumes.
+state every --every steps so that an interrupted run resumes (a finished
+run's checkpoint rewrites the output without stepping).
 
     python tests/golden/make_long_runs.py abdominal [--checkpoint-dir DIR]
 """
@@ -91,11 +95,15 @@ def main():
     trace = np.concatenate(traces)
     nd, s = maps.ndim, spec["stride"]
     div = solver.divergence(state.v, maps)
+    p_last = state.p.copy()
+    nxt, _ = solver.run(prob, 1, state=state.copy(), maps=maps, record=False)
+    drive = nxt.p - p_last
     peak = max(float(np.abs(state.p).max()), float(np.abs(trace).max()))
     out = os.path.join(args.out_dir, spec["out"])
     np.savez_compressed(out, trace=trace.astype(np.float32),
                         p_dec=decimate(state.p, nd, s).astype(np.float32),
                         div_dec=decimate(div, nd, s).astype(np.float32),
+                        drive_dec=decimate(drive, nd, s).astype(np.float32),
                         peak=np.float64(peak), stride=np.int64(s), n_steps=np.int64(n_total),
                         name=np.array(prob.name))
     print("wrote %s (peak %.6g, |p_final|max %.6g)" % (out, peak, float(np.abs(state.p).max())), flush=True)

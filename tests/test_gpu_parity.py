@@ -1,13 +1,20 @@
 """GPU parity: the HIP library (through the C ABI) against the FP64 oracle on
 the same seeded inputs.
 
-Bar: relative L2 <= 1e-4 and max-abs <= 1e-3 of the peak pressure for p and
-the receiver traces.  The velocity and the memory variables are held to the
-same max-abs bound after conversion to pressure units (rho c |dv|,
-h |dpsi1|, h rho c |dpsi2|): once a pulse has passed, FP32 rounding leaves a
-small non-radiating residual in v (a discretely divergence-free field that
-neither drives nor feels p), so their final values can be tiny and a
-relative L2 of them measures that residual rather than the solution.
+Bar: relative L2 <= 1e-4 and max-abs <= 1e-3 of the peak pressure.
+  - p and the receiver traces: both, always (the relative L2 of the final p
+    is waived only when the pulse has left the grid and the final field is
+    below 1e-5 of the peak: it then measures FP32 rounding of a residue).
+  - v, psi1, psi2: max-abs after conversion to pressure units (rho c |dv|,
+    h |dpsi1|, h rho c |dpsi2|), always.  While the pulse is in the grid
+    (final max|p| at least a tenth of the peak) each is also held to the
+    relative L2 bar.  After it has left, FP32 rounding leaves a small
+    residual in v and psi2 that the pressure phase does not feel (their
+    relative L2 can exceed 1e-4 while p stays within 1e-5); there the
+    combination of v and psi2 that drives p, the pressure phase's S (one
+    oracle step's pressure increment from the GPU state against that from
+    the oracle state), is held to the relative L2 bar, waived below 1e-5 of
+    the peak like p.  The divergence of v is printed beside them.
 Every test prints its case before touching the GPU."""
 import numpy as np
 import pytest
@@ -19,6 +26,8 @@ pytestmark = pytest.mark.gpu
 
 REL_L2 = 1e-4
 MAX_ABS = 1e-3
+DECAYED = 1e-5          # final field below this fraction of the peak: the pulse has left the grid
+LIVE = 0.1              # final max|p| at least this fraction of the peak: the pulse is in the grid
 
 
 def _torch():
@@ -67,29 +76,64 @@ def rel_l2(a, b):
     return np.linalg.norm(a - b) / nb if nb > 0 else np.linalg.norm(a)
 
 
+def pressure_drive(prob, fields, step, maps):
+    """One oracle step's pressure increment from the given state: -dt S / K
+    plus the sources of that step, where S is what the pressure phase forms
+    from v and psi2 (the part of the state that drives p)."""
+    st = solver.State(prob.ndim, prob.n_relax, tuple(prob.shape[::-1]))
+    st.p, st.v = fields["p"].astype(np.float64), fields["v"].astype(np.float64)
+    st.psi1, st.psi2 = fields["psi1"].astype(np.float64), fields["psi2"].astype(np.float64)
+    st.step = int(step)
+    p0 = st.p.copy()
+    s1, _ = solver.run(prob, 1, st, maps=maps, record=False)
+    return s1.p - p0
+
+
 def compare(f, tr, ref, rtr, label, check_all=True, prob=None):
+    """Prints every figure, then asserts the bars (module docstring)."""
     peak = np.abs(ref.p).max()
     if rtr is not None and rtr.size:
         peak = max(peak, np.abs(rtr).max())
     e_p = rel_l2(f["p"], ref.p)
     m_p = np.abs(f["p"] - ref.p).max() / peak
-    _say(label, "p rel %.2e max/peak %.2e" % (e_p, m_p))
-    assert e_p <= REL_L2, (label, e_p)
-    assert m_p <= MAX_ABS, (label, m_p)
+    a_p = np.abs(ref.p).max() / peak
+    _say(label, "p rel %.2e max/peak %.2e (final max|p| %.1e of peak)" % (e_p, m_p, a_p))
     if rtr is not None and rtr.size:
         e_t = rel_l2(tr[:rtr.shape[0]], rtr)
         m_t = np.abs(tr[:rtr.shape[0]] - rtr).max() / peak
         _say(label, "trace rel %.2e max/peak %.2e" % (e_t, m_t))
-        assert e_t <= REL_L2 and m_t <= MAX_ABS, (label, e_t, m_t)
+    fields = []
     if check_all:
         z = float(np.max(np.asarray(prob.rho, np.float64) * np.asarray(prob.c, np.float64)))
         h = prob.h
         scale = {"v": z, "psi1": h, "psi2": h * z}
         for name in ("v", "psi1", "psi2"):
-            d = np.abs(f[name] - getattr(ref, name)).max() * scale[name] / peak
-            _say(label, "%s max-abs (pressure units)/peak %.2e, rel L2 %.2e"
-                 % (name, d, rel_l2(f[name], getattr(ref, name))))
-            assert d <= MAX_ABS, (label, name, d)
+            r = getattr(ref, name)
+            d = np.abs(f[name] - r).max() * scale[name] / peak
+            a = np.abs(r).max() * scale[name] / peak
+            e = rel_l2(f[name], r)
+            fields.append((name, d, a, e))
+            _say(label, "%s max-abs (pressure units)/peak %.2e, rel L2 %.2e (max %.1e of peak)" % (name, d, e, a))
+        maps = solver.stencil_maps(prob)
+        e_d = rel_l2(solver.divergence(f["v"], maps), solver.divergence(ref.v, maps))
+        _say(label, "div(v) rel L2 %.2e" % e_d)
+        drive = None
+        if a_p < LIVE or prob.ndim == 2 or np.prod(prob.shape) <= 2e6:
+            cm = solver.coefficient_maps(prob)
+            gd = pressure_drive(prob, f, ref.step, cm)
+            rd = pressure_drive(prob, {"p": ref.p, "v": ref.v, "psi1": ref.psi1, "psi2": ref.psi2}, ref.step, cm)
+            drive = (rel_l2(gd, rd), np.abs(rd).max() / peak)
+            _say(label, "pressure drive rel L2 %.2e (max %.1e of peak)" % drive)
+    assert m_p <= MAX_ABS, (label, m_p)
+    assert e_p <= REL_L2 or a_p < DECAYED, (label, e_p)
+    if rtr is not None and rtr.size:
+        assert e_t <= REL_L2 and m_t <= MAX_ABS, (label, e_t, m_t)
+    for name, d, a, e in fields:
+        assert d <= MAX_ABS, (label, name, d)
+        if a_p >= LIVE:
+            assert e <= REL_L2, (label, name, e)
+    if check_all and a_p < LIVE:
+        assert drive[0] <= REL_L2 or drive[1] < DECAYED, (label, "pressure drive", drive)
 
 
 def _state(prob, seed):
@@ -125,6 +169,38 @@ def test_heterogeneous_2d_small_grid():
     f, tr, _ = gpu_run(prob, prob.n_steps)
     ref, rtr = oracle_run(prob, prob.n_steps)
     compare(f, tr, ref, rtr, "abdominal_2d_small", prob=prob)
+
+
+def test_heterogeneous_2d_mid_run_all_fields():
+    """The heterogeneous recipe on 320 x 224 after 300 steps, while the pulse
+    is inside the grid: every field, v and the memory variables included."""
+    prob = W.abdominal_2d(nx=320, ny=224, n_steps=300, n_scatter=2000)
+    _say("abdominal_2d 320x224 L=4 300 steps (pulse in the grid)")
+    f, tr, _ = gpu_run(prob, prob.n_steps)
+    ref, rtr = oracle_run(prob, prob.n_steps)
+    compare(f, tr, ref, rtr, "abdominal_2d_small_300", prob=prob)
+
+
+def test_heterogeneous_2d_stated_step_count_small_grid():
+    """The abdominal recipe for its stated 12000 steps on a 320 x 224 grid
+    (FP32 drift over the whole run; the full-size grid is compared with
+    stored oracle results in test_gpu_long_runs)."""
+    prob = W.abdominal_2d(nx=320, ny=224, n_steps=12000, n_scatter=2000)
+    _say("abdominal_2d 320x224 L=4 12000 steps")
+    f, tr, _ = gpu_run(prob, prob.n_steps)
+    ref, rtr = oracle_run(prob, prob.n_steps)
+    _say("final max|p| / peak trace %.3e" % (np.abs(ref.p).max() / np.abs(rtr).max()))
+    compare(f, tr, ref, rtr, "abdominal_2d_small_12000", prob=prob)
+
+
+def test_skull_3d_stated_step_count_small_cube():
+    """The transcranial recipe for its stated 4000 steps on a 64^3 cube."""
+    prob = W.skull_3d(n=64, nb=10, ntr=6, n_steps=4000)
+    _say("skull_3d 64^3 L=2 4000 steps")
+    f, tr, _ = gpu_run(prob, prob.n_steps)
+    ref, rtr = oracle_run(prob, prob.n_steps)
+    _say("final max|p| / peak trace %.3e" % (np.abs(ref.p).max() / np.abs(rtr).max()))
+    compare(f, tr, ref, rtr, "skull_3d_64_4000", prob=prob)
 
 
 def test_heterogeneous_2d_full_size_random_state():
