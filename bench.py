@@ -220,6 +220,20 @@ def probe_copy(torch, dev, mib, reps=10):
     return {"bytes_per_copy": moved, "ms": round(ms, 4), "GBps": round(moved / ms / 1e6, 1), "reps": reps}
 
 
+def stream_reference(torch, dev, roofline, mib=2048):
+    """What a plain device copy streams on this GPU, beside the dominant
+    kernel's algorithmic rate and its measured HBM traffic rate."""
+    ref = probe_copy(torch, dev, mib)
+    out = {"kind": "plain device-to-device copy (one torch copy kernel)", "bytes_per_copy": ref["bytes_per_copy"],
+           "ms": ref["ms"], "GBps": ref["GBps"], "reps": ref["reps"],
+           "kernel_algorithmic_over_copy": round(roofline["achieved"] / ref["GBps"], 3)}
+    if roofline.get("traffic"):
+        traffic_gbs = roofline["traffic"] / (roofline["launch_ms"] * 1e-3) / 1e9
+        out["kernel_traffic_GBps"] = round(traffic_gbs, 1)
+        out["kernel_traffic_over_copy"] = round(traffic_gbs / ref["GBps"], 3)
+    return out
+
+
 STATED_SERVING_REQUESTS = 256     # the served workload's stream
 
 
@@ -720,6 +734,8 @@ def main():
     ap.add_argument("--no-slab", action="store_true", help="skip the slab (one GPU's share) leg")
     ap.add_argument("--no-abdominal", action="store_true",
                     help="with the 3D headline, skip the 2D abdominal-wall sub-object")
+    ap.add_argument("--no-stream-reference", action="store_true",
+                    help="skip the plain-copy streaming reference beside the headline roofline")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first time a plain device copy of this size (bandwidth reference, "
                          "and the known-size kernel for scaling HBM counters)")
@@ -769,6 +785,8 @@ def main():
     print("[bench] headline %s: %.3f Gpoint-updates/s" % (prob.name, head["value"]), file=sys.stderr, flush=True)
     if copy_probe is not None:
         out["copy_probe"] = copy_probe
+    if not args.no_stream_reference:
+        out["stream_reference"] = stream_reference(torch, dev, out["roofline"])
     if not args.no_local_stencil:
         out["local_stencil"] = local_stencil_leg(prob, max(1, min(K, 2000)))
     if three_d and not args.no_slab and prob.shape[2] >= 512:

@@ -71,3 +71,15 @@ def test_workload_names_carry_the_mechanism_count():
         bench.make_workload("plain_2d", relax=3)
     with pytest.raises(ValueError):
         bench.make_workload("skull_3d", 32, 4)
+
+
+def test_stream_reference_relates_the_kernel_to_a_plain_copy(monkeypatch):
+    import bench
+    monkeypatch.setattr(bench, "probe_copy", lambda torch, dev, mib, reps=10: {
+        "bytes_per_copy": 2 * mib * (1 << 20), "ms": 1.0, "GBps": 5000.0, "reps": reps})
+    roof = {"achieved": 4000.0, "traffic": 10 * 10 ** 9, "launch_ms": 2.0}
+    r = bench.stream_reference(None, None, roof)
+    assert r["kernel_algorithmic_over_copy"] == 0.8
+    assert r["kernel_traffic_GBps"] == 5000.0 and r["kernel_traffic_over_copy"] == 1.0
+    r = bench.stream_reference(None, None, {"achieved": 4000.0, "traffic": None, "launch_ms": 2.0})
+    assert "kernel_traffic_GBps" not in r
