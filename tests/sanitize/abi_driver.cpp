@@ -175,6 +175,7 @@ static void null_checks()
     int64_t cnt[2];
     CHECK(fw2_step(nullptr, 1) == FW2_E_STATE);
     CHECK(fw2_step_phase(nullptr, 0) == FW2_E_STATE);
+    CHECK(fw2_step_into(nullptr, 1, nullptr, nullptr) == FW2_E_STATE);
     CHECK(fw2_halo_bytes(nullptr, FW2_HALO_P, &b) == FW2_E_STATE);
     CHECK(fw2_halo_pack(nullptr, FW2_HALO_P, FW2_LOW, nullptr) == FW2_E_STATE);
     CHECK(fw2_halo_unpack(nullptr, FW2_HALO_V, FW2_HIGH, nullptr) == FW2_E_STATE);
