@@ -19,7 +19,8 @@ def test_stored_long_run_matches_its_workload(fname, make, stride):
     prob = make()
     assert str(z["name"]) == prob.name
     assert int(z["n_steps"]) == prob.n_steps and int(z["stride"]) == stride
-    assert z["trace"].shape == (prob.n_steps, len(prob.rcv_idx))
+    rs = int(z["rcv_stride"])
+    assert z["trace"].shape == (prob.n_steps, len(range(0, len(prob.rcv_idx), rs)))
     dec = tuple(len(range(0, n, stride)) for n in prob.shape[::-1])
     for key in ("p_dec", "div_dec", "drive_dec"):
         assert z[key].shape == dec, key

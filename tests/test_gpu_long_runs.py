@@ -3,8 +3,8 @@
 max-abs <= 1e-3 of the peak pressure after the stated step count).
 
 The oracle needs hours for these, so its results are stored:
-tests/golden/make_long_runs.py (which calls only the oracle) wrote every
-receiver trace, the final pressure on a decimated subgrid and the divergence
+tests/golden/make_long_runs.py (which calls only the oracle) wrote the
+receiver traces (every one in 2D, every 4th in 3D), the final pressure on a decimated subgrid and the divergence
 sum_a D^-_a v_a of the final velocity on the same subgrid.  The GPU runs the
 same seeded inputs through the C ABI in the benchmark's launch configuration
 (graph chunks of 32 steps, default kernels).
@@ -62,6 +62,7 @@ def test_stated_step_count_matches_the_oracle(case):
     dom.destroy_domain()
     peak = float(ref["peak"])
     rtr = ref["trace"].astype(np.float64)
+    tr = tr[:, ::int(ref["rcv_stride"])]
     e_t, m_t = _rel(tr, rtr), float(np.abs(tr - rtr).max() / peak)
     sl = (slice(None, None, s),) * prob.ndim
     p = f["p"][sl].astype(np.float64)
