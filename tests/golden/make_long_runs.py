@@ -4,8 +4,7 @@ Calls only the oracle (and the seeded input generator).  Each run takes a
 workload at its stated step count and stores, in float32:
 
   trace     receiver traces, [n_steps][n_rcv / rcv_stride]: every
-            rcv_stride-th receiver (all of them in 2D; every 4th of the 1024
-            in 3D, to keep the file small)
+            rcv_stride-th receiver (1 for both runs: every receiver)
   p_dec     the final pressure on a decimated subgrid (every `stride`-th
             point along each axis, starting at 0)
   div_dec   the divergence sum_a D^-_a v_a of the final velocity at the same
@@ -19,7 +18,7 @@ Workloads:
   abdominal   the 2D heterogeneous abdominal-wall recipe, 4096 x 2048, L = 4,
               12000 steps (stride 8)
   skull256    the 3D transcranial recipe on a 256^3 cube, L = 2, 4000 steps
-              (stride 4, every 4th receiver)
+              (stride 4)
 
 The oracle needs hours on a few cores for each; --checkpoint-dir keeps the
 state every --every steps so that an interrupted run resumes (a finished
@@ -44,7 +43,7 @@ from oracle import solver  # noqa: E402
 RUNS = {
     "abdominal": dict(make=lambda: W.abdominal_2d(), stride=8, rcv_stride=1,
                       out="long_abdominal_2d_4096x2048.npz"),
-    "skull256": dict(make=lambda: W.skull_3d(n=256), stride=4, rcv_stride=4,
+    "skull256": dict(make=lambda: W.skull_3d(n=256), stride=4, rcv_stride=1,
                      out="long_skull_3d_256.npz"),
 }
 

@@ -10,7 +10,8 @@ import workloads as W
 
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
-FILES = [("long_abdominal_2d_4096x2048.npz", lambda: W.abdominal_2d(), 8)]
+FILES = [("long_abdominal_2d_4096x2048.npz", lambda: W.abdominal_2d(), 8),
+         ("long_skull_3d_256.npz", lambda: W.skull_3d(n=256), 4)]
 
 
 @pytest.mark.parametrize("fname,make,stride", FILES, ids=[f[0] for f in FILES])
