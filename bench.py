@@ -709,6 +709,36 @@ def measure(prob, K, Wm):
             "setup_s": round(setup_s, 3)}
 
 
+def launch_leg(steps=1000):
+    """The launch-bound workload (plain_2d: 480^2 points, about 23 MB moved
+    per step): time per step with the steps captured in HIP graphs of 32 and
+    with direct launches, beside the time the step's algorithmic bytes take
+    at the HBM peak."""
+    import torch
+    from paper_2106_11476_amd import fw2
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(device=dev)
+    prob = make_workload("plain_2d")
+    dom = fw2.from_problem(prob, device=dev, stream=stream, cap_steps=steps)
+    dom.step(steps)
+    torch.cuda.synchronize(dev)
+    out = {"workload": prob.name, "points": prob.npts, "steps": steps}
+    for mode, chunk in (("graph", 32), ("direct", 0)):
+        dom.set_graph_chunk(chunk)
+        torch.cuda.synchronize(dev)
+        t0 = time.perf_counter()
+        dom.step(steps)
+        torch.cuda.synchronize(dev)
+        el = time.perf_counter() - t0
+        out[mode] = {"ms_per_step": round(el / steps * 1e3, 5), "gpts": round(prob.npts * steps / el / 1e9, 3)}
+    dom.destroy_domain()
+    labels = prob.label is not None and np.asarray(prob.relax_table).shape[0] > 1
+    step_b = kernel_bytes(prob.ndim, prob.n_relax, labels)[2]
+    out["alg_bytes_per_step"] = step_b * prob.npts
+    out["hbm_peak_ms_per_step"] = round(step_b * prob.npts / (HBM_PEAK_GBS * 1e9) * 1e3, 5)
+    return out
+
+
 def main():
     global PROFILES
     ap = argparse.ArgumentParser()
@@ -734,6 +764,8 @@ def main():
     ap.add_argument("--no-slab", action="store_true", help="skip the slab (one GPU's share) leg")
     ap.add_argument("--no-abdominal", action="store_true",
                     help="with the 3D headline, skip the 2D abdominal-wall sub-object")
+    ap.add_argument("--no-launch-bound", action="store_true",
+                    help="skip the launch-bound workload (plain_2d, graphs against direct launches)")
     ap.add_argument("--no-stream-reference", action="store_true",
                     help="skip the plain-copy streaming reference beside the headline roofline")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -787,6 +819,8 @@ def main():
         out["copy_probe"] = copy_probe
     if not args.no_stream_reference:
         out["stream_reference"] = stream_reference(torch, dev, out["roofline"])
+    if not args.no_launch_bound:
+        out["launch_bound"] = launch_leg()
     if not args.no_local_stencil:
         out["local_stencil"] = local_stencil_leg(prob, max(1, min(K, 2000)))
     if three_d and not args.no_slab and prob.shape[2] >= 512:
