@@ -2,11 +2,15 @@
 fix: free-space Green's function, plane-wave attenuation / dispersion
 (Sec. 4.1, Fig. 2), two-stage C-PML reflection (Secs. 4.2-4.3, Fig. 3) and
 nonlinear steepening against the exact pre-shock simple wave (Sec. 4.5)."""
+import json
+import os
+import sys
+
 import numpy as np
 import pytest
 
 import workloads as W
-from oracle import physics, reflection, relaxation, solver
+from oracle import physics, relaxation, solver
 
 C0 = 1540.0
 
@@ -146,14 +150,28 @@ def test_printed_recursion_loses_attenuation(oracle_lib):
 
 
 # ----------------------------------------------------- C-PML reflection (E2/E3) ---
+# The reflection sweeps take minutes, so tests/golden/make_reflection_figures.py
+# (oracle only) stores the measured figures; the pins below read them, and
+# test_stored_reflection_figures_match_the_oracle recomputes one case.
 
-_reflection_db = reflection.reflection_db
+_FIG = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
-ANGLES = (0, 20, 45, 60, 70, 80)
+def _figures():
+    with open(os.path.join(_FIG, "reflection_figures.json")) as fh:
+        return {k: np.array(v["dB"]) for k, v in json.load(fh).items()}
 
 
-def test_cpml_reflection_over_the_stated_angles(oracle_lib, golden):
+def test_stored_reflection_figures_match_the_oracle(oracle_lib):
+    """The stored figures are the current oracle's: one case (Table 2 verbatim,
+    3 + 1 lambda, normal incidence) recomputed gives the stored value."""
+    sys.path.insert(0, _FIG)
+    import make_reflection_figures as mk
+    key, row, L, angles, kw = [c for c in mk.cases() if c[0] == "table2 3+1"][0]
+    assert np.allclose(mk.measure(row, L, angles, kw), _figures()[key], atol=1e-6, rtol=0)
+
+
+def test_cpml_reflection_over_the_stated_angles(golden):
     """Secs. 4.2-4.3 at 16 ppw, CFL 0.2, 3 lambda transition + 1 lambda bound:
     the stated bound of about -49 dB from 0 to 80 degrees and the -50 dB of
     the 3 + 1 lambda layer, read from the fixture.  R_c is not stated: with
@@ -165,13 +183,13 @@ def test_cpml_reflection_over_the_stated_angles(oracle_lib, golden):
     the angle: the minimum near 45 degrees of the paper's figure is not
     reproduced (recorded finding)."""
     st = golden.stated()
+    fig = _figures()
     bound, b31 = st["reflection_db_all_angles_max"], st["reflection_db_tr3_bd1"]
     assert (st["ppw_reflection"], st["cfl_reflection"]) == (16, 0.2)
-    r = _reflection_db(W.lossless_row(1), 1, ANGLES, pml_Rc=1e-4)
+    r = fig["lossless 3+1 R_c 1e-4"]
     assert np.all(r <= bound), r
     assert r[0] <= b31, r
-    row = W.tissue_row(0.5, 1.0, 2, 2e6)
-    rf = _reflection_db(row, 2, ANGLES)
+    rf = fig["fitted 3+1"]
     assert rf[0] <= b31, rf
     assert np.all(rf[:4] <= bound), rf                       # 0 .. 60 degrees
     assert -49.0 < rf[4] < -44.0 and -38.0 < rf[5] < -31.0, rf   # 70, 80 degrees: above the bound
@@ -179,7 +197,7 @@ def test_cpml_reflection_over_the_stated_angles(oracle_lib, golden):
         assert np.all(np.diff(curve) > 0), curve
 
 
-def test_cpml_reflection_thickness_and_table2(oracle_lib, golden):
+def test_cpml_reflection_thickness_and_table2(golden):
     """Sec. 4.2: about -50 dB with a 3 + 1 lambda layer and -60 dB with
     5 + 1 lambda, read from the fixture, at normal incidence.  The lossless
     special case meets the 5 + 1 figure with the library's R_c = 1e-3 (and
@@ -195,14 +213,15 @@ def test_cpml_reflection_thickness_and_table2(oracle_lib, golden):
     (oracle reading "A_alpha_tr", a study reading, not the library's) brings
     Table 2 below -50 dB at R_c = 1e-3."""
     st = golden.stated()
+    fig = _figures()
     b31, b51 = st["reflection_db_tr3_bd1"], st["reflection_db_tr5_bd1"]
-    assert _reflection_db(W.lossless_row(1), 1, (0,), ntr_l=5)[0] <= b51
-    t3 = _reflection_db(W.TABLE2_ROW, 2, (0,))[0]
+    assert fig["lossless 5+1"][0] <= b51
+    t3 = fig["table2 3+1"][0]
     assert -42.0 < t3 < -35.0, t3
-    t3e = _reflection_db(W.TABLE2_ROW, 2, (0,), pml_Rc=1e-5)[0]
+    t3e = fig["table2 3+1 R_c 1e-5"][0]
     assert t3e <= b31 and -24.0 < t3e - t3 < -17.0, (t3, t3e)
-    assert _reflection_db(W.TABLE2_ROW, 2, (0,), ntr_l=5, pml_Rc=1e-5)[0] <= b51
-    ta = _reflection_db(W.TABLE2_ROW, 2, (0,), pml_reading="A_alpha_tr")[0]
+    assert fig["table2 5+1 R_c 1e-5"][0] <= b51
+    ta = fig["table2 3+1 alpha over the transition"][0]
     assert ta <= b31 and ta < t3 - 10.0, (t3, ta)
 
 
