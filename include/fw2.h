@@ -241,9 +241,11 @@ fw2_status fw2_check_finite(fw2_domain *dom, float limit);
  * destination blocks.
  * n = 0 does nothing (the pointers may then be NULL).
  * Asynchronous on the domain's stream; the n steps are captured in a HIP
- * graph (reused while dev_first, dev_states and n stay the same) unless
- * graphs are off (fw2_set_graph_chunk 0) or kernel timing is on.  Slabs:
- * FW2_E_UNSUPPORTED.
+ * graph (reused while dev_first, dev_states and n stay the same, dropped
+ * when sources or receivers change) unless graphs are off
+ * (fw2_set_graph_chunk 0) or kernel timing is on.  Errors: n < 0, a NULL or
+ * misaligned block pointer, or an overlap: FW2_E_INVALID; a half-done step
+ * (fw2_step_phase): FW2_E_STATE; slabs: FW2_E_UNSUPPORTED.
  *
  * The discrete adjoint (the paper's extension to full waveform inversion,
  * Sec. 5: the memory-variable recursion is dissipative, so the reverse step
