@@ -102,3 +102,11 @@ def test_step_into_checks_its_arguments():
     torch.cuda.synchronize()
     assert d.current_step() == 1
     d.destroy_domain()
+    from paper_2106_11476_amd import slab
+    cube = W.skull_3d(n=32, nb=6, ntr=4, n_steps=4)
+    part = slab.split_problem(cube, [0, 16, 32], only=[0])[0][0]
+    s = fw2.Domain(part, device="cuda:0")
+    sb = s.new_state_buffer(3)
+    with pytest.raises(fw2.Fw2Error):
+        s.step_into(2, sb[0], sb[1:])               # slabs exchange halos between phases
+    s.destroy_domain()
