@@ -885,7 +885,7 @@ fw2_status enqueue_step_into(fw2_domain *d, const float *src, float *dst, hipStr
     a.v = a.p + S;
     a.psi1 = a.p + (int64_t)(1 + nd) * S;
     a.psi2 = a.psi1 + (int64_t)nd * L * S;
-    a.out = dst - src;
+    a.out = ((int64_t)(uintptr_t)dst - (int64_t)(uintptr_t)src) / 4;   // both 4-byte aligned
     FW2_HIP(fw2::launch_pressure(a, L, sch, d->kc, s));
     fw2::SparseArgs src_pts = d->src, rcv = d->rcv;
     src_pts.p = dst;
