@@ -237,7 +237,7 @@ def stream_reference(torch, dev, roofline, mib=2048):
 STATED_SERVING_REQUESTS = 256     # the served workload's stream
 
 
-def serving_leg(seed=4, workload_requests=8, only_workload=False):
+def serving_leg(seed=4, workload_requests=8, only_workload=False, solo_points=1_000_000, solo_chunk=512):
     """Continuous batching vs the plain one-at-a-time solver on four seeded
     request streams of the heterogeneous 2D recipe: `workload_requests` of
     the served workload's requests (1024^2-3072^2 at their own step counts;
@@ -273,7 +273,8 @@ def serving_leg(seed=4, workload_requests=8, only_workload=False):
         med = float(np.median([serve.footprint_bytes(p, k) for p, k, _ in raw]))
         budget = int(24 * med)
         p0 = serve.run_plain(mk([0.0] * n))
-        srv = serve.Server(budget_bytes=budget, max_active=32, chunk=64, tile=tile)
+        srv = serve.Server(budget_bytes=budget, max_active=32, chunk=64, tile=tile, solo_points=solo_points,
+                           solo_chunk=solo_chunk)
         b0 = srv.run(mk([0.0] * n))
         lam = 1.2 * p0.completed / p0.makespan
         arr = np.cumsum(np.random.default_rng(seed + 40).exponential(1.0 / lam, n))
@@ -753,6 +754,10 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the batched-serving leg")
     ap.add_argument("--serving-requests", type=int, default=8,
                     help="requests of the served workload's stream (the stated stream has 256)")
+    ap.add_argument("--serving-solo-points", type=int, default=1_000_000,
+                    help="serving: requests of at least this many points are stepped alone")
+    ap.add_argument("--serving-solo-chunk", type=int, default=512,
+                    help="serving: steps between admission points while a solo request runs")
     ap.add_argument("--serving-only-workload", action="store_true",
                     help="serving leg: only the served workload's stream")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint (gradient) leg")
@@ -840,7 +845,8 @@ def main():
         print("[bench] 2D workload done", file=sys.stderr, flush=True)
     if not args.no_serving:
         out["serving"] = serving_leg(workload_requests=args.serving_requests,
-                                     only_workload=args.serving_only_workload)
+                                     only_workload=args.serving_only_workload,
+                                     solo_points=args.serving_solo_points, solo_chunk=args.serving_solo_chunk)
         print("[bench] serving leg done", file=sys.stderr, flush=True)
     if not args.no_adjoint:
         out["adjoint"] = adjoint_leg(steps=args.adjoint_steps)

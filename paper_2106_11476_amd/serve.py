@@ -92,6 +92,10 @@ class Server:
     max_active   -- largest number of requests advanced by one launch (<= 64)
     chunk        -- steps between admission / completion points
     solo_points  -- requests of at least this many points are stepped alone
+    solo_chunk   -- steps between those points while a solo request runs
+                    (newcomers cannot run before it finishes, so its chunks
+                    can be longer; the host turnaround at each boundary
+                    leaves the device idle)
 
     Host work overlaps device work: arrived requests are admitted (arrival
     order, memory budget and slots counted over running, built and admitted
@@ -115,7 +119,7 @@ class Server:
     """
 
     def __init__(self, budget_bytes, max_active=32, chunk=64, device="cuda:0", tile=(256, 4),
-                 solo_points=2_000_000):
+                 solo_points=1_000_000, solo_chunk=512):
         import torch
         self.torch = torch
         self.device = torch.device(device)
@@ -128,6 +132,7 @@ class Server:
         self.tile = tuple(tile)
         self.batch.set_tile(*tile)
         self.solo_points = int(solo_points)
+        self.solo_chunk = int(solo_chunk) if solo_chunk else self.chunk
 
     def _start(self, r):
         dom = fw2.Domain(r.problem, device=self.device, stream=self.setup_stream)
@@ -228,7 +233,8 @@ class Server:
             left = [r.n_steps - d.current_step() for r, d in (active if run_batch else solo[:1])]
             to_done = min(left)
             waiting = pending or (queue and len(active) + len(solo) < self.max_active)
-            k = max(int(min(to_done, self.chunk) if waiting else to_done), 1)
+            chunk = self.chunk if run_batch else self.solo_chunk
+            k = max(int(min(to_done, chunk) if waiting else to_done), 1)
             if run_batch:
                 self.batch.step(k)
             else:
