@@ -314,7 +314,7 @@ void fw2_batch_destroy(fw2_batch *b);
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, serving loops that must not call hipMalloc, harnesses that forbid
  * it): fw2_batch_create without a workspace.  The batch uses the library's
- * own table, a file-scope device array of sizeof the 64-domain table (45 KiB,
+ * own table, a file-scope device array of sizeof the 64-domain table (46 KiB,
  * one per GPU, held until the process ends), instead of caller memory; the
  * call allocates no device memory.  max_domains is 1..64 (FW2_E_INVALID
  * beyond: the table holds 64 domains).  The table is cleared by this call
