@@ -237,7 +237,8 @@ def stream_reference(torch, dev, roofline, mib=2048):
 STATED_SERVING_REQUESTS = 256     # the served workload's stream
 
 
-def serving_leg(seed=4, workload_requests=8, only_workload=False, solo_points=1_000_000, solo_chunk=512):
+def serving_leg(seed=4, workload_requests=8, only_workload=False, solo_points=1_000_000, solo_chunk=512,
+                passes="all", rate=None):
     """Continuous batching vs the plain one-at-a-time solver on four seeded
     request streams of the heterogeneous 2D recipe: `workload_requests` of
     the served workload's requests (1024^2-3072^2 at their own step counts;
@@ -246,7 +247,9 @@ def serving_leg(seed=4, workload_requests=8, only_workload=False, solo_points=1_
     launch class (3, 4 or 8 mechanisms; every third request with per-point
     stencil weights).  Capacity: all requests queued at t = 0.  Latency:
     Poisson arrivals at 1.2x the plain solver's capacity.  target_met: the
-    batched capacity is at least twice the plain one."""
+    batched capacity is at least twice the plain one.  passes: "all", or
+    "capacity" or "poisson" alone (the latter at the given arrival rate), so
+    that a long stream can be measured in two runs."""
     import workloads as W
     from paper_2106_11476_amd import fw2, serve
     out = {}
@@ -272,28 +275,41 @@ def serving_leg(seed=4, workload_requests=8, only_workload=False, solo_points=1_
         tile, _ = serve.autotune_tile(tune, steps=32)
         med = float(np.median([serve.footprint_bytes(p, k) for p, k, _ in raw]))
         budget = int(24 * med)
-        p0 = serve.run_plain(mk([0.0] * n))
         srv = serve.Server(budget_bytes=budget, max_active=32, chunk=64, tile=tile, solo_points=solo_points,
                            solo_chunk=solo_chunk)
-        b0 = srv.run(mk([0.0] * n))
-        lam = 1.2 * p0.completed / p0.makespan
-        arr = np.cumsum(np.random.default_rng(seed + 40).exponential(1.0 / lam, n))
-        pl = serve.run_plain(mk(arr))
-        bt = srv.run(mk(arr))
+
+        def progress(label):
+            # long streams: a line every 16 completed requests
+            def done(r, _c=[0]):
+                _c[0] += 1
+                if _c[0] % 16 == 0:
+                    print("[serving] %s %s: %d of %d done" % (name, label, _c[0], n), file=sys.stderr, flush=True)
+            return done
+        res = {"requests": n, "sides": list(sides), "relax_mechanisms": list(L_choices),
+               "per_point_weights_every": local_every, "tile": list(tile), "budget_bytes": budget}
+        lam = rate
+        if passes in ("all", "capacity"):
+            p0 = serve.run_plain(mk([0.0] * n), on_done=progress("capacity plain"))
+            b0 = srv.run(mk([0.0] * n), on_done=progress("capacity served"))
+            lam = 1.2 * p0.completed / p0.makespan
+            res.update({
+                "capacity_sims_per_s": {"plain": round(p0.completed / p0.makespan, 3),
+                                        "batched": round(b0.completed / b0.makespan, 3)},
+                "capacity_gpoint_updates_per_s": {"plain": round(upd / p0.makespan / 1e9, 3),
+                                                  "batched": round(upd / b0.makespan / 1e9, 3)},
+                "capacity_speedup": round(p0.makespan / b0.makespan, 3),
+                "target_met": bool(p0.makespan / b0.makespan >= 2.0),
+                "capacity_host_s": {"plain": p0.summary()["host_s"], "batched": b0.summary()["host_s"]}})
+        if passes in ("all", "poisson"):
+            if not lam:
+                raise SystemExit("the Poisson pass alone needs --serving-rate")
+            arr = np.cumsum(np.random.default_rng(seed + 40).exponential(1.0 / lam, n))
+            pl = serve.run_plain(mk(arr), on_done=progress("poisson plain"))
+            bt = srv.run(mk(arr), on_done=progress("poisson served"))
+            res.update({"poisson_rate_per_s": round(lam, 3),
+                        "poisson": {"plain": pl.summary(), "batched": bt.summary()}})
         srv.close()
-        out[name] = {
-            "requests": n, "sides": list(sides), "relax_mechanisms": list(L_choices),
-            "per_point_weights_every": local_every, "tile": list(tile), "budget_bytes": budget,
-            "capacity_sims_per_s": {"plain": round(p0.completed / p0.makespan, 3),
-                                    "batched": round(b0.completed / b0.makespan, 3)},
-            "capacity_gpoint_updates_per_s": {"plain": round(upd / p0.makespan / 1e9, 3),
-                                              "batched": round(upd / b0.makespan / 1e9, 3)},
-            "capacity_speedup": round(p0.makespan / b0.makespan, 3),
-            "target_met": bool(p0.makespan / b0.makespan >= 2.0),
-            "capacity_host_s": {"plain": p0.summary()["host_s"], "batched": b0.summary()["host_s"]},
-            "poisson_rate_per_s": round(lam, 3),
-            "poisson": {"plain": pl.summary(), "batched": bt.summary()},
-        }
+        out[name] = res
         if name == "workload_1024_3072":
             out[name]["stated_stream_requests"] = STATED_SERVING_REQUESTS
             out[name]["subsample"] = n < STATED_SERVING_REQUESTS
@@ -758,6 +774,10 @@ def main():
                     help="serving: requests of at least this many points are stepped alone")
     ap.add_argument("--serving-solo-chunk", type=int, default=512,
                     help="serving: steps between admission points while a solo request runs")
+    ap.add_argument("--serving-passes", choices=("all", "capacity", "poisson"), default="all",
+                    help="serving: both passes, or the capacity or the Poisson pass alone")
+    ap.add_argument("--serving-rate", type=float, default=None,
+                    help="serving: arrival rate per second of the Poisson pass run alone")
     ap.add_argument("--serving-only-workload", action="store_true",
                     help="serving leg: only the served workload's stream")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint (gradient) leg")
@@ -846,7 +866,8 @@ def main():
     if not args.no_serving:
         out["serving"] = serving_leg(workload_requests=args.serving_requests,
                                      only_workload=args.serving_only_workload,
-                                     solo_points=args.serving_solo_points, solo_chunk=args.serving_solo_chunk)
+                                     solo_points=args.serving_solo_points, solo_chunk=args.serving_solo_chunk,
+                                     passes=args.serving_passes, rate=args.serving_rate)
         print("[bench] serving leg done", file=sys.stderr, flush=True)
     if not args.no_adjoint:
         out["adjoint"] = adjoint_leg(steps=args.adjoint_steps)

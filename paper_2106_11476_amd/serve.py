@@ -141,8 +141,9 @@ class Server:
         dom.add_receivers(r.problem.rcv_idx, r.n_steps)
         return dom
 
-    def run(self, requests, clock=time.perf_counter):
-        """Serve the requests (sorted by arrival); returns Stats."""
+    def run(self, requests, clock=time.perf_counter, on_done=None):
+        """Serve the requests (sorted by arrival); returns Stats.  on_done(r),
+        if given, is called as each request completes."""
         queue = sorted(requests, key=lambda r: (r.arrival, r.rid))
         if self.tile[0] != 256 and any(int(r.problem.n_relax) > 4 and r.problem.npts < self.solo_points
                                        for r in queue):
@@ -199,6 +200,8 @@ class Server:
                         r.done = clock() - t0
                         stats.latencies.append(r.done - r.arrival)
                         stats.completed += 1
+                        if on_done:
+                            on_done(r)
                     stats.t_finish += clock() - tf
             for r, d in staged:
                 if r.problem.npts >= self.solo_points:
@@ -249,8 +252,9 @@ class Server:
         self.batch.destroy()
 
 
-def run_plain(requests, device="cuda:0", clock=time.perf_counter):
-    """The same requests one at a time in arrival order (single-domain path)."""
+def run_plain(requests, device="cuda:0", clock=time.perf_counter, on_done=None):
+    """The same requests one at a time in arrival order (single-domain path);
+    on_done(r), if given, is called as each request completes."""
     import torch
     dev = torch.device(device)
     stream = torch.cuda.Stream(device=dev)
@@ -279,6 +283,8 @@ def run_plain(requests, device="cuda:0", clock=time.perf_counter):
         stats.latencies.append(r.done - r.arrival)
         stats.completed += 1
         stats.peak_active = 1
+        if on_done:
+            on_done(r)
     stats.makespan = clock() - t0
     return stats
 
