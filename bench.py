@@ -237,12 +237,12 @@ def stream_reference(torch, dev, roofline, mib=2048):
 STATED_SERVING_REQUESTS = 256     # the served workload's stream
 
 
-def serving_leg(seed=4, workload_requests=8, only_workload=False, solo_points=1_000_000, solo_chunk=512,
+def serving_leg(seed=4, workload_requests=16, only_workload=False, solo_points=1_000_000, solo_chunk=512,
                 passes="all", rate=None):
     """Continuous batching vs the plain one-at-a-time solver on four seeded
     request streams of the heterogeneous 2D recipe: `workload_requests` of
     the served workload's requests (1024^2-3072^2 at their own step counts;
-    the stated stream has 256, the default 8 is a subsample), 48 at
+    the stated stream has 256, the default 16 is a subsample), 48 at
     512^2-1024^2, 96 small 128^2-384^2 grids, and 48 small grids mixing every
     launch class (3, 4 or 8 mechanisms; every third request with per-point
     stencil weights).  Capacity: all requests queued at t = 0.  Latency:
@@ -768,7 +768,7 @@ def main():
                     help="relaxation mechanisms (abdominal_2d: 3..8, default 4; skull_3d: 2 or 5..8, default 2)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true", help="skip the batched-serving leg")
-    ap.add_argument("--serving-requests", type=int, default=8,
+    ap.add_argument("--serving-requests", type=int, default=16,
                     help="requests of the served workload's stream (the stated stream has 256)")
     ap.add_argument("--serving-solo-points", type=int, default=1_000_000,
                     help="serving: requests of at least this many points are stepped alone")
