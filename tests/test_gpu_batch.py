@@ -132,10 +132,12 @@ def test_serving_steps_large_requests_alone_in_arrival_order():
     solo = [_solo(p, n)[1] for p, n in mix]
     reqs = [serve.Request(rid=i, problem=p, n_steps=n, arrival=0.002 * i) for i, (p, n) in enumerate(mix)]
     budget = int(4 * max(serve.footprint_bytes(p, n) for p, n in mix))
-    srv = serve.Server(budget_bytes=budget, max_active=4, chunk=48, solo_points=cut)
-    st = srv.run(reqs)
+    srv = serve.Server(budget_bytes=budget, max_active=4, chunk=48, solo_points=cut, solo_chunk=16)
+    seen = []
+    st = srv.run(reqs, on_done=lambda r: seen.append(r.rid))
     srv.close()
     assert st.completed == len(mix) and st.peak_bytes <= budget
+    assert seen == [r.rid for r in sorted(reqs, key=lambda r: r.done)]          # one call per completion
     for r, tr in zip(reqs, solo):
         assert np.array_equal(r.trace, tr), r.rid
     big = [r for r in reqs if r.problem.npts >= cut]

@@ -20,6 +20,8 @@ CASES = [
     ((37, 21, 19), 2, 1, None),            # 3D plane sweeps (default variant)
     ((37, 21, 19), 3, 0, "0,32,16"),       # 3D generic kernels
     ((40, 33, 30), 2, 1, "1,32,16"),       # 3D plane sweeps without prefetch
+    ((131, 90), 3, 1, "local"),            # per-point stencil weights, 2D
+    ((37, 21, 19), 2, 0, "local"),         # per-point stencil weights, 3D
 ]
 
 
@@ -42,10 +44,12 @@ def _problem(shape, L, scheme, n_steps):
 def test_steps_into_blocks_are_the_in_place_states(monkeypatch, shape, L, scheme, config, graph):
     torch = _torch()
     from paper_2106_11476_amd import fw2
-    if config:
+    if config and config != "local":
         monkeypatch.setenv("FW2_KERNEL_CONFIG", config)
     n0, n = 5, 9
     prob = _problem(shape, L, scheme, n0 + n)
+    if config == "local":
+        prob.stencil_mode = fw2.STENCIL_LOCAL
     st = _state(prob, 23)
     _say("step_into", shape, "L", L, "scheme", scheme, "config", config, "graph", graph)
     a = fw2.from_problem(prob, device="cuda:0", cap_steps=n0 + n)
