@@ -246,3 +246,29 @@ def test_autotuner_keeps_256_columns_for_many_mechanisms():
     probs = [p for p, _ in _variant_mix()[1:3]]
     best, t = serve.autotune_tile(probs, candidates=((256, 4), (64, 8)), steps=8)
     assert best == (256, 4) and set(t) == {(256, 4)}
+
+
+def test_served_workload_request_matches_the_oracle():
+    """Requests of the served workload's recipe at their own size and step
+    count (1024^2, 2560 steps, L and f0 as the stream draws them), served
+    together in the batched launch (no solo threshold): the first one's
+    traces against the oracle at the parity bar (relative L2 <= 1e-4,
+    max-abs <= 1e-3 of the peak)."""
+    _torch()
+    from paper_2106_11476_amd import serve
+    from test_gpu_parity import oracle_run, rel_l2
+    raw = W.serving_requests(n=3, seed=4, sides=(1024, 1024))
+    _say("served workload, three 1024^2 requests batched", [(p.n_relax, n) for p, n, _ in raw])
+    reqs = [serve.Request(rid=i, problem=p, n_steps=n, arrival=0.0) for i, (p, n, _) in enumerate(raw)]
+    budget = int(4 * max(serve.footprint_bytes(p, n) for p, n, _ in raw))
+    srv = serve.Server(budget_bytes=budget, max_active=4, chunk=64, solo_points=1 << 40)
+    st = srv.run(reqs)
+    srv.close()
+    assert st.completed == 3 and st.peak_active == 3
+    p0, n0, _ = raw[0]
+    _, rtr = oracle_run(p0, n0)
+    peak = np.abs(rtr).max()
+    e = rel_l2(reqs[0].trace[:n0], rtr)
+    m = np.abs(reqs[0].trace[:n0] - rtr).max() / peak
+    _say("request 0 (L %d, %d steps): trace rel L2 %.2e, max/peak %.2e" % (p0.n_relax, n0, e, m))
+    assert e <= 1e-4 and m <= 1e-3
