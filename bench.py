@@ -280,10 +280,13 @@ def serving_leg(seed=4, workload_requests=16, only_workload=False, solo_points=1
 
         def progress(label):
             # long streams: a line every 16 completed requests
-            def done(r, _c=[0]):
-                _c[0] += 1
-                if _c[0] % 16 == 0:
-                    print("[serving] %s %s: %d of %d done" % (name, label, _c[0], n), file=sys.stderr, flush=True)
+            count = 0
+
+            def done(r):
+                nonlocal count
+                count += 1
+                if count % 16 == 0:
+                    print("[serving] %s %s: %d of %d done" % (name, label, count, n), file=sys.stderr, flush=True)
             return done
         res = {"requests": n, "sides": list(sides), "relax_mechanisms": list(L_choices),
                "per_point_weights_every": local_every, "tile": list(tile), "budget_bytes": budget}
