@@ -1260,28 +1260,39 @@ fw2_status fw2_batch_set_domains(fw2_batch *b, int32_t n, fw2_domain *const *dom
     fw2::BatchTable &T = b->host;
     std::memset(&T, 0, sizeof(T));
     T.rows = b->rows;
-    int tiles = 0;
+    int tiles = 0, m = 0;
     unsigned classes = 0;
     for (int32_t k = 0; k < n; ++k) {
         fw2_domain *d = domains[k];
         classes |= 1u << fw2::batch_class(d->desc.n_relax, d->args.local_stencil);
         // the domain's own queued work must be finished before the batch stream touches it
         FW2_HIP(hipStreamSynchronize(d->stream));
-        fw2::BatchEntry &e = T.e[k];
-        e.a = d->args;
-        e.src = d->src;
-        e.rcv = d->rcv;
-        e.n_steps = n_steps[k];
-        e.L = d->desc.n_relax;
-        e.scheme = d->desc.relax_scheme;
-        const int nbx = (d->ly.geo.n[0] + b->bx - 1) / b->bx;
-        const int nby = (d->ly.geo.n[1] + b->rows - 1) / b->rows;
-        e.tiles = nbx * nby;
-        e.tile_base = tiles;
-        tiles += e.tiles;
         b->doms.push_back(d);
         b->target.push_back(n_steps[k]);
     }
+    // entries grouped by launch class, so that each class launch walks only
+    // its own tiles, spread over every XCD
+    for (int c = 0; c < 4; ++c) {
+        T.class_begin[c] = tiles;
+        for (int32_t k = 0; k < n; ++k) {
+            fw2_domain *d = domains[k];
+            if (fw2::batch_class(d->desc.n_relax, d->args.local_stencil) != c) continue;
+            fw2::BatchEntry &e = T.e[m++];
+            e.a = d->args;
+            e.src = d->src;
+            e.rcv = d->rcv;
+            e.n_steps = n_steps[k];
+            e.L = d->desc.n_relax;
+            e.scheme = d->desc.relax_scheme;
+            const int nbx = (d->ly.geo.n[0] + b->bx - 1) / b->bx;
+            const int nby = (d->ly.geo.n[1] + b->rows - 1) / b->rows;
+            e.tiles = nbx * nby;
+            e.tile_base = tiles;
+            tiles += e.tiles;
+        }
+        T.class_end[c] = tiles;
+    }
+    if (m != n) return fail(FW2_E_INVALID, "a domain of no launch class");
     T.n = n;
     T.total_tiles = tiles;
     if (classes != b->classes) batch_drop_graph(b);    // the captured launches differ

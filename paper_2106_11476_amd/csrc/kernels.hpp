@@ -125,6 +125,9 @@ struct BatchTable {
     int32_t n;
     int32_t total_tiles;
     int32_t rows;                    // tile rows; tile columns bx = 64 or 256
+    // Entries are ordered by launch class; the tiles of class c are
+    // [class_begin[c], class_end[c]) of the tile list.
+    int32_t class_begin[4], class_end[4];
     BatchEntry e[kMaxBatch];
 };
 

@@ -1103,7 +1103,8 @@ __device__ __forceinline__ void batch_dispatch(int key, const StepArgs &sa, int 
 // 5..8 mechanisms (else 1..4), bit 1 set for per-point stencil weights.
 // Each class present gets a launch of its own, so that the larger register
 // demand of many mechanisms or per-point weights does not lower the
-// occupancy of the common class; entries of other classes are skipped.
+// occupancy of the common class; entries are grouped by class, and each
+// launch walks only its class's range of the tile list.
 template <bool PRESSURE, int BX, int CLASS>
 __global__ void __launch_bounds__(BX) batch_phase(const BatchTable *__restrict__ T)
 {
@@ -1111,11 +1112,12 @@ __global__ void __launch_bounds__(BX) batch_phase(const BatchTable *__restrict__
     __shared__ float r0[4][BX + 8];
     __shared__ float r1[3][BX + 2];
     __shared__ float r2[3][BX + 1];
-    const int total = T->total_tiles, rows = T->rows;
+    // the class's own tiles: entries are grouped by class, so they are one
+    // contiguous range of the tile list
+    const int begin = T->class_begin[CLASS], total = T->class_end[CLASS] - begin, rows = T->rows;
     // Blocks are dealt to the 8 XCDs round-robin; with a grid that is a
     // multiple of 8, the blocks of XCD x walk one contiguous eighth of the
-    // tile list, so neighbouring tiles (which share halo rows) meet in the
-    // same L2.
+    // range, so neighbouring tiles (which share halo rows) meet in the same L2.
     int t = blockIdx.x, t_end = total, t_step = gridDim.x;
     if (gridDim.x % 8 == 0) {
         const int x = blockIdx.x % 8, q = total / 8, rem = total % 8;
@@ -1125,9 +1127,10 @@ __global__ void __launch_bounds__(BX) batch_phase(const BatchTable *__restrict__
         t_step = gridDim.x / 8;
     }
     for (; t < t_end; t += t_step) {
-        const int d = batch_entry_of_tile(T, t);
+        const int tile = begin + t;
+        const int d = batch_entry_of_tile(T, tile);
         const BatchEntry &e = T->e[d];
-        if (batch_class(e.L, e.a.local_stencil) != CLASS) continue;     // uniform over the block
+        if (batch_class(e.L, e.a.local_stencil) != CLASS) continue;     // (never: the range is the class's)
         const long long step = *e.rcv.step;
         // pressure phase of step s runs while the counter reads s; velocity after it moved to s + 1
         const bool active = PRESSURE ? step < e.n_steps : (step >= 1 && step <= e.n_steps);
@@ -1137,7 +1140,7 @@ __global__ void __launch_bounds__(BX) batch_phase(const BatchTable *__restrict__
         // own arguments do
         const StepArgs &sa = e.a;
         const int nbx = (sa.geo.n[0] + BX - 1) / BX;
-        const int lt = t - e.tile_base;
+        const int lt = tile - e.tile_base;
         const int x0 = (lt % nbx) * BX, y0 = (lt / nbx) * rows;
         const int key = (e.L - (MANY ? 5 : 1)) * 2 + e.scheme;
         batch_dispatch<PRESSURE, BX, MANY ? 5 : 1, PP>(key, sa, rows, x0, y0, r0, r1, r2);
