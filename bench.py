@@ -220,17 +220,49 @@ def probe_copy(torch, dev, mib, reps=10):
     return {"bytes_per_copy": moved, "ms": round(ms, 4), "GBps": round(moved / ms / 1e6, 1), "reps": reps}
 
 
+def library_probe(torch, dev, kind, nbytes, reps=10):
+    """HBM rate of one of the library's streaming probes (fw2_stream_probe)
+    over a device buffer of nbytes, timed with events on torch's current
+    stream, which the probe is launched on."""
+    from paper_2106_11476_amd import fw2
+    buf = torch.zeros(nbytes, dtype=torch.uint8, device=dev)
+    n = fw2.stream_probe_elements(kind, nbytes)
+    moved = 2 * 16 * n if kind == fw2.PROBE_COPY else 21 * 4 * n
+    for _ in range(2):
+        fw2.stream_probe(kind, buf)
+    torch.cuda.synchronize(dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fw2.stream_probe(kind, buf)
+    e1.record()
+    torch.cuda.synchronize(dev)
+    ms = e0.elapsed_time(e1) / reps
+    del buf
+    return {"bytes": moved, "ms": round(ms, 4), "GBps": round(moved / ms / 1e6, 1), "reps": reps}
+
+
 def stream_reference(torch, dev, roofline, mib=2048):
-    """What a plain device copy streams on this GPU, beside the dominant
-    kernel's algorithmic rate and its measured HBM traffic rate."""
+    """What plain streaming kernels reach on this GPU, beside the dominant
+    kernel's algorithmic rate and its measured HBM traffic rate: torch's
+    device copy, the library's one-thread-per-float4 copy, and the library's
+    probe with the velocity phase's byte mix (12 arrays read, 9 written, 4 B
+    per lane, no stencil)."""
+    from paper_2106_11476_amd import fw2
     ref = probe_copy(torch, dev, mib)
     out = {"kind": "plain device-to-device copy (one torch copy kernel)", "bytes_per_copy": ref["bytes_per_copy"],
            "ms": ref["ms"], "GBps": ref["GBps"], "reps": ref["reps"],
            "kernel_algorithmic_over_copy": round(roofline["achieved"] / ref["GBps"], 3)}
+    copy16 = library_probe(torch, dev, fw2.PROBE_COPY, 2 * mib << 20)
+    mix = library_probe(torch, dev, fw2.PROBE_VELOCITY_MIX, 21 * (512 << 20))
+    out["probe_copy16"] = dict(copy16, kind="fw2_stream_probe copy, one float4 per thread")
+    out["probe_velocity_mix"] = dict(mix, kind="fw2_stream_probe, 12 FP32 arrays read and 9 written per point")
+    out["kernel_algorithmic_over_copy16"] = round(roofline["achieved"] / copy16["GBps"], 3)
     if roofline.get("traffic"):
         traffic_gbs = roofline["traffic"] / (roofline["launch_ms"] * 1e-3) / 1e9
         out["kernel_traffic_GBps"] = round(traffic_gbs, 1)
         out["kernel_traffic_over_copy"] = round(traffic_gbs / ref["GBps"], 3)
+        out["kernel_traffic_over_velocity_mix"] = round(traffic_gbs / mix["GBps"], 3)
     return out
 
 

@@ -378,6 +378,25 @@ fw2_status fw2_halo_pack(fw2_domain *dom, int32_t kind, int32_t side, void *dev_
 fw2_status fw2_halo_unpack(fw2_domain *dom, int32_t kind, int32_t side, const void *dev_src);
 fw2_status fw2_step_phase(fw2_domain *dom, int32_t phase);
 
+/* Library infrastructure (measurement): streaming probes.  Plain one-thread-
+ * per-element kernels whose HBM rate is the reference for the step kernels'
+ * measured traffic; they compute nothing of the method.
+ *   FW2_PROBE_COPY          copies the first half of buf to the second, 16
+ *                           bytes per thread (bytes / 32 float4 elements);
+ *   FW2_PROBE_VELOCITY_MIX  the velocity phase's per-point byte mix at L = 2
+ *                           in 3D without its stencil: buf holds 21 FP32
+ *                           arrays of n = floor(bytes / 84 / 64) * 64 points,
+ *                           one after another; every point reads x_0..x_11
+ *                           (arrays 0..11) and writes t = (x_0 + x_4) + x_5,
+ *                           x_{1+q} + t (q < 3, arrays 12..14) and
+ *                           fma(0.5, x_{6+q}, t) (q < 6, arrays 15..20).
+ * buf: caller-owned device memory, 256-byte aligned, overwritten where
+ * written; bytes in [64 KiB, 1 TiB].  Asynchronous on stream (hipStream_t;
+ * NULL: the default stream).  Errors: FW2_E_INVALID for an unknown kind, a
+ * NULL or misaligned buf or bytes out of range. */
+enum { FW2_PROBE_COPY = 0, FW2_PROBE_VELOCITY_MIX = 1 };
+fw2_status fw2_stream_probe(int32_t kind, void *dev_buf, uint64_t bytes, void *stream);
+
 /* Library infrastructure.  Message of the last failed call on this thread ("" if none). */
 const char *fw2_last_error(void);
 

@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "kernels.hpp"
+#include "probe.hpp"
 #include "setup.hpp"
 
 namespace {
@@ -1100,6 +1101,16 @@ fw2_status fw2_halo_unpack(fw2_domain *d, int32_t kind, int32_t side, const void
     if (st != FW2_OK) return st;
     if (!dev_src) return fail(FW2_E_INVALID, "src is NULL");
     FW2_HIP(fw2::launch_unpack(halo_planes(d, kind, side, true), d->ly.geo, (const float *)dev_src, d->stream));
+    return FW2_OK;
+}
+
+fw2_status fw2_stream_probe(int32_t kind, void *dev_buf, uint64_t bytes, void *stream)
+{
+    if (kind != FW2_PROBE_COPY && kind != FW2_PROBE_VELOCITY_MIX) return fail(FW2_E_INVALID, "unknown probe kind");
+    if (!dev_buf) return fail(FW2_E_INVALID, "buf is NULL");
+    if ((uintptr_t)dev_buf % kAlign != 0) return fail(FW2_E_INVALID, "buf must be 256-byte aligned");
+    if (bytes < 64 * 1024 || bytes > ((uint64_t)1 << 40)) return fail(FW2_E_INVALID, "bytes must lie in [64 KiB, 1 TiB]");
+    FW2_HIP(fw2::launch_stream_probe(kind, dev_buf, bytes, (hipStream_t)stream));
     return FW2_OK;
 }
 

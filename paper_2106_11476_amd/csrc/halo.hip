@@ -1,11 +1,12 @@
 // gfx950 kernels of libfw2 around the time step: the halo planes of a slab
-// of a grid split along z (pack / unpack), and the medium of a domain built
-// from device maps.
+// of a grid split along z (pack / unpack), the medium of a domain built
+// from device maps, and the streaming probes of the measurement.
 //
-// Both are plain streaming kernels (bandwidth bound, no reuse): one thread
+// All are plain streaming kernels (bandwidth bound, no reuse): one thread
 // per element, consecutive threads on consecutive x, so every wavefront
 // reads and writes 256 contiguous bytes.
 #include "kernels.hpp"
+#include "probe.hpp"
 
 #include <algorithm>
 
@@ -111,6 +112,72 @@ hipError_t launch_medium(const MediumArgs &m, hipStream_t st)
 {
     const dim3 grid((m.geo.n[0] + 255) / 256, std::min(m.geo.n[1], kMaxGridYZ), std::min(m.geo.n[2], kMaxGridYZ));
     hipLaunchKernelGGL(medium_kernel, grid, dim3(256), 0, st, m);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Streaming probes (measurement).  They give the HBM rate that a plain
+// kernel of a given access pattern reaches on the device, the reference
+// against which the step kernels' measured traffic is read.  One thread per
+// element, no loop, so the resident waves always cover one compact address
+// window.
+// ---------------------------------------------------------------------------
+
+namespace {
+
+constexpr int kProbeBX = 256;
+
+__global__ void __launch_bounds__(kProbeBX) probe_copy16(const float4 *__restrict__ src, float4 *__restrict__ dst,
+                                                         uint64_t n)
+{
+    const uint64_t i = blockIdx.x * (uint64_t)kProbeBX + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+
+// The velocity phase's per-point byte mix at L = 2 in 3D without its
+// stencil: 12 FP32 arrays read (p, three v, rho, kappa0, six memory
+// variables), 9 written (three v, six memory variables).
+struct MixArgs {
+    const float *r[12];
+    float *w[9];
+};
+
+__global__ void __launch_bounds__(kProbeBX) probe_mix(const MixArgs m, uint64_t n)
+{
+    const uint64_t i = blockIdx.x * (uint64_t)kProbeBX + threadIdx.x;
+    if (i >= n) return;
+    float x[12];
+#pragma unroll
+    for (int q = 0; q < 12; ++q) x[q] = m.r[q][i];
+    const float t = (x[0] + x[4]) + x[5];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) m.w[q][i] = x[1 + q] + t;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) m.w[3 + q][i] = fmaf(0.5f, x[6 + q], t);
+}
+
+}  // namespace
+
+uint64_t stream_probe_elements(int kind, uint64_t bytes)
+{
+    if (kind == 0) return bytes / 32;                         // float4 pairs: half read, half written
+    return bytes / (21 * 4) / 64 * 64;                         // points per array, arrays 256-byte aligned
+}
+
+hipError_t launch_stream_probe(int kind, void *buf, uint64_t bytes, hipStream_t stream)
+{
+    const uint64_t n = stream_probe_elements(kind, bytes);
+    const unsigned blocks = (unsigned)((n + kProbeBX - 1) / kProbeBX);
+    if (kind == 0) {
+        const float4 *src = (const float4 *)buf;
+        hipLaunchKernelGGL(probe_copy16, dim3(blocks), dim3(kProbeBX), 0, stream, src, (float4 *)buf + n, n);
+    } else {
+        MixArgs m;
+        float *f = (float *)buf;
+        for (int q = 0; q < 12; ++q) m.r[q] = f + (uint64_t)q * n;
+        for (int q = 0; q < 9; ++q) m.w[q] = f + (uint64_t)(12 + q) * n;
+        hipLaunchKernelGGL(probe_mix, dim3(blocks), dim3(kProbeBX), 0, stream, m, n);
+    }
     return hipGetLastError();
 }
 

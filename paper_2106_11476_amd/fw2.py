@@ -21,6 +21,7 @@ RELAX_PRINTED, RELAX_CENTRED = 0, 1
 STENCIL_GLOBAL, STENCIL_LOCAL = 0, 1
 NL_PRINTED, NL_CUSTOM = 0, 1
 HALO_P, HALO_V, HALO_MEDIUM = 0, 1, 2
+PROBE_COPY, PROBE_VELOCITY_MIX = 0, 1
 LOW, HIGH = 0, 1
 PHASE_PRESSURE, PHASE_VELOCITY = 0, 1
 MAX_LABELS = 256
@@ -34,7 +35,7 @@ EXPORTS = ["fw2_workspace_bytes", "fw2_create_domain", "fw2_add_source", "fw2_ad
            "fw2_state_bytes", "fw2_save_state", "fw2_load_state", "fw2_adjoint_workspace_bytes",
            "fw2_adjoint_begin", "fw2_adjoint_step", "fw2_adjoint_gradient",
            "fw2_label_relaxation_map", "fw2_halo_bytes", "fw2_halo_pack", "fw2_halo_unpack",
-           "fw2_step_phase", "fw2_batch_create_noalloc", "fw2_step_into"]
+           "fw2_step_phase", "fw2_batch_create_noalloc", "fw2_step_into", "fw2_stream_probe"]
 
 
 class Fw2Error(RuntimeError):
@@ -103,6 +104,7 @@ def lib():
             "fw2_halo_unpack": [vp, i32, i32, vp],
             "fw2_step_phase": [vp, i32],
             "fw2_batch_create_noalloc": [i32, vp, ctypes.POINTER(vp)],
+            "fw2_stream_probe": [i32, vp, u64, vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -167,6 +169,21 @@ def make_desc(prob, stream=None):
     d.slab_z0 = int(getattr(prob, "slab_z0", 0))
     d.slab_nz = int(getattr(prob, "slab_nz", 0))
     return d, keep
+
+
+def stream_probe_elements(kind, nbytes):
+    """Elements the probe of `kind` covers in a buffer of nbytes: float4
+    copies for PROBE_COPY, points per array for PROBE_VELOCITY_MIX."""
+    return nbytes // 32 if kind == PROBE_COPY else nbytes // 84 // 64 * 64
+
+
+def stream_probe(kind, buf, stream=None):
+    """Run fw2_stream_probe over the device buffer `buf` (a torch tensor),
+    asynchronously on `stream` (default: torch's current stream)."""
+    import torch
+    st = stream if stream is not None else torch.cuda.current_stream(buf.device)
+    _check(lib().fw2_stream_probe(int(kind), ctypes.c_void_p(buf.data_ptr()), buf.numel() * buf.element_size(),
+                                  ctypes.c_void_p(st.cuda_stream)))
 
 
 def label_relaxation_map(maps, n_relax):
