@@ -187,6 +187,13 @@ static void null_checks()
     CHECK(fw2_batch_create_noalloc(65, nullptr, &bt) == FW2_E_INVALID && bt == nullptr);
     CHECK(fw2_batch_create_noalloc(4, nullptr, &bt) != FW2_OK && bt == nullptr);
     CHECK(fw2_current_step(nullptr) == -1);
+    alignas(256) static unsigned char probe_buf[512];
+    CHECK(fw2_stream_probe(7, probe_buf, 1 << 20, nullptr) == FW2_E_INVALID);
+    CHECK(fw2_stream_probe(FW2_PROBE_COPY, nullptr, 1 << 20, nullptr) == FW2_E_INVALID);
+    CHECK(fw2_stream_probe(FW2_PROBE_COPY, probe_buf + 4, 1 << 20, nullptr) == FW2_E_INVALID);
+    CHECK(fw2_stream_probe(FW2_PROBE_VELOCITY_MIX, probe_buf, 1024, nullptr) == FW2_E_INVALID);
+    CHECK(fw2_stream_probe(FW2_PROBE_VELOCITY_MIX, probe_buf, ((uint64_t)1 << 40) + 1, nullptr) == FW2_E_INVALID);
+    CHECK(fw2_stream_probe(FW2_PROBE_COPY, probe_buf, 1 << 20, nullptr) == FW2_E_HIP);   // the stub launcher: no device
     fw2_destroy_domain(nullptr);
     fw2_batch_destroy(nullptr);
 }

@@ -3,6 +3,7 @@
 // enqueue nothing and report that there is no device.  Linked only into
 // tests/sanitize/abi_driver; the library itself never uses it.
 #include "kernels.hpp"
+#include "probe.hpp"
 
 namespace fw2 {
 
@@ -16,6 +17,7 @@ hipError_t launch_set_counter(long long *, long long, hipStream_t) { return hipE
 hipError_t launch_pack(const PlaneSet &, const Geometry &, float *, hipStream_t) { return hipErrorNoDevice; }
 hipError_t launch_unpack(const PlaneSet &, const Geometry &, const float *, hipStream_t) { return hipErrorNoDevice; }
 hipError_t launch_medium(const MediumArgs &, hipStream_t) { return hipErrorNoDevice; }
+hipError_t launch_stream_probe(int, void *, uint64_t, hipStream_t) { return hipErrorNoDevice; }
 hipError_t launch_batch_step(const BatchTable *, int, int, unsigned, hipStream_t) { return hipErrorNoDevice; }
 void prepare_batch_launches() {}
 hipError_t claim_static_batch_table(int, BatchTable **table, bool *busy)
