@@ -74,12 +74,21 @@ def test_workload_names_carry_the_mechanism_count():
 
 
 def test_stream_reference_relates_the_kernel_to_a_plain_copy(monkeypatch):
+    """The stream reference relates the dominant kernel's algorithmic and
+    measured-traffic rates to torch's copy and to the library's probes."""
     import bench
+    from paper_2106_11476_amd import fw2
     monkeypatch.setattr(bench, "probe_copy", lambda torch, dev, mib, reps=10: {
         "bytes_per_copy": 2 * mib * (1 << 20), "ms": 1.0, "GBps": 5000.0, "reps": reps})
+    rates = {fw2.PROBE_COPY: 6250.0, fw2.PROBE_VELOCITY_MIX: 5200.0}
+    monkeypatch.setattr(bench, "library_probe", lambda torch, dev, kind, nbytes, reps=10: {
+        "bytes": nbytes, "ms": 1.0, "GBps": rates[kind], "reps": reps})
     roof = {"achieved": 4000.0, "traffic": 10 * 10 ** 9, "launch_ms": 2.0}
     r = bench.stream_reference(None, None, roof)
     assert r["kernel_algorithmic_over_copy"] == 0.8
     assert r["kernel_traffic_GBps"] == 5000.0 and r["kernel_traffic_over_copy"] == 1.0
+    assert r["kernel_algorithmic_over_copy16"] == 0.64
+    assert r["kernel_traffic_over_velocity_mix"] == round(5000.0 / 5200.0, 3)
+    assert r["probe_copy16"]["GBps"] == 6250.0 and r["probe_velocity_mix"]["GBps"] == 5200.0
     r = bench.stream_reference(None, None, {"achieved": 4000.0, "traffic": None, "launch_ms": 2.0})
     assert "kernel_traffic_GBps" not in r
