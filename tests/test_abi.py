@@ -108,6 +108,12 @@ def test_two_dimensional_grids_just_below_the_offset_limit_are_accepted():
     prob = W.plain_2d()
     prob.shape = (32000, 33000)
     assert fw2.workspace_bytes(prob) > 32000 * 33000 * 4
+    prob.shape = (32697, 32759)                     # (nx + 72)(ny + 8) = 2^30 - 1: the largest accepted
+    assert fw2.workspace_bytes(prob) > 32697 * 32759 * 4
+    for shape in ((32698, 32759), (32697, 32760)):  # one column or one row more
+        prob.shape = shape
+        with pytest.raises(fw2.Fw2Error, match="2\\^30"):
+            fw2.workspace_bytes(prob)
 
 
 def _slab_problem(**kw):

@@ -382,6 +382,87 @@ def test_skull_3d_full_size_window():
     compare(f, None, ref, None, "skull_3d_1024_window", prob=small)
 
 
+def test_largest_2d_grid_far_corner_window():
+    """The largest 2D grid the library accepts, 32697 x 32759 ((nx + 72)(ny + 8)
+    = 2^30 - 1; padded rows of 32768 floats, so the sweeps' 32-bit byte offsets
+    reach 4.29e9 of the 2^32 they can hold), in the default launch
+    configuration with graph-captured steps, checked where the oracle can
+    follow it: a 128^2 window at the far corner (the highest offsets, and the
+    far boundary layers) holds a heterogeneous two-tissue medium, and a seeded
+    random state fills a 16^2 block 16 cells from both far edges, inside the
+    far layers.  After 3 steps the pressure reaches the far edges, and every
+    nonzero sample lies within 28 cells of the block.  The same
+    window as its own 128^2 grid (same h, dt, stencil r, layer constants and
+    48-cell layers, so its far layers are the big grid's) run by the oracle
+    must give the same fields over the whole window."""
+    torch = _torch()
+    from paper_2106_11476_amd import fw2
+    nx, ny, n, blk, steps = 32697, 32759, 128, 16, 3
+    h = W.grid_spacing(1540.0, 1e6, 12)
+    c_max = 3080.0
+    dt = 0.4 * h / c_max
+    rows = np.asarray([W.TABLE2_ROW, W.tissue_row(8.0, 1.0, 2, 1e6)], np.float64)
+    rng = np.random.default_rng(32697)
+    wc = rng.uniform(1540.0, c_max, (n, n)).astype(np.float32)
+    wr = (1040.0 + (wc - 1540.0) * (860.0 / 1540.0)).astype(np.float32)
+    wb = rng.uniform(3.5, 5.5, (n, n)).astype(np.float32)
+    wl = (wc > 2300.0).astype(np.uint8)
+
+    def problem(gx, gy):
+        arr = (gy, gx)
+        return W.Problem(shape=(gx, gy), h=h, dt=dt, n_relax=2, c=np.full(arr, 1540.0, np.float32),
+                         rho=np.full(arr, 1040.0, np.float32), beta=np.full(arr, 4.0, np.float32),
+                         relax_table=rows, label=np.zeros(arr, np.uint8), bound_cells=(48, 48),
+                         trans_cells=(36, 36), pml_cp=c_max, fd_r=c_max * dt / h, n_steps=steps)
+
+    small = problem(n, n)
+    small.c[...], small.rho[...], small.beta[...], small.label[...] = wc, wr, wb, wl
+    st = {"p": np.zeros((n, n), np.float32), "v": np.zeros((2, n, n), np.float32),
+          "psi1": np.zeros((2, 2, n, n), np.float32), "psi2": np.zeros((2, 2, n, n), np.float32)}
+    b0 = n - 16 - blk
+    inner = (slice(b0, b0 + blk),) * 2
+    for name, arr in zip(("p", "v", "psi1", "psi2"), W.random_state(2, 2, (blk,) * 2, 78)):
+        st[name][(Ellipsis,) + inner] = arr
+
+    big = problem(nx, ny)
+    win = (slice(ny - n, ny), slice(nx - n, nx))
+    big.c[win], big.rho[win], big.beta[win], big.label[win] = wc, wr, wb, wl
+    _say("largest 2D grid %dx%d, far-corner %d^2 window, random %d^2 block, %d steps (graph chunk 2)"
+         % (nx, ny, n, blk, steps))
+    dom = fw2.from_problem(big, device="cuda:0", cap_steps=steps)
+    del big
+    dom.set_graph_chunk(2)
+    buf = torch.zeros(dom.field_numel(), dtype=torch.float32, device="cuda:0")
+    views = dom.field_views(buf)
+    for name, arr in st.items():
+        views[name][(Ellipsis,) + win] = torch.from_numpy(arr).to("cuda:0")
+    dom.write_fields_device(buf)
+    del buf, views
+    dom.step(steps)
+    torch.cuda.synchronize()
+    out = dom.read_fields_device()
+    views = dom.field_views(out)
+    f = {name: views[name][(Ellipsis,) + win].cpu().numpy() for name in st}
+    for name in st:                      # every sample outside the window is still exactly zero
+        views[name][(Ellipsis,) + win] = 0.0
+    outside = float(out.abs().max().item())
+    del out, views
+    dom.destroy_domain()
+    torch.cuda.empty_cache()
+    assert outside == 0.0, outside
+    ref, _ = oracle_run(small, steps, state=st)
+    # nothing reached the window's near layers (an 8-cell margin is zero); the
+    # far edges, shared with the big grid, are reached
+    for name in st:
+        a = np.abs(getattr(ref, name))
+        for ax in range(2):
+            lo = [slice(None)] * a.ndim
+            lo[a.ndim - 2 + ax] = slice(0, 8)
+            assert a[tuple(lo)].max() == 0.0, (name, ax)
+    assert np.abs(ref.p[:, -1]).max() > 0 and np.abs(ref.p[-1, :]).max() > 0
+    compare(f, None, ref, None, "largest_2d_far_corner", prob=small)
+
+
 # ---------------------------------------------------------- edge cases ---
 
 def test_degenerate_grids():
