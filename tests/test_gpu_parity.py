@@ -463,6 +463,78 @@ def test_largest_2d_grid_far_corner_window():
     compare(f, None, ref, None, "largest_2d_far_corner", prob=small)
 
 
+def test_largest_3d_cube_far_corner_window():
+    """A 1400^3 cube, about the largest that fits the GPU's memory (a 215 GB
+    workspace; every array holds 2.74e9 > 2^31 elements), in the default
+    launch configuration: a 128^3 window at its far corner (the highest
+    addresses, and the far boundary layers) holds a heterogeneous two-tissue
+    medium, a point source 52 cells from the far faces plays a seeded random
+    signal, and 27 receivers sit around it and inside the far layers.  After
+    40 steps the wave has moved a few cells; what the stencil carries further
+    is below FP32 range long before the window's near faces.  The same window
+    as its own 128^3 grid (same h, dt, stencil r, layer constants, 48-cell
+    layers) run by the oracle must give the same traces and final pressure
+    in the window."""
+    torch = _torch()
+    from paper_2106_11476_amd import fw2
+    torch.cuda.empty_cache()
+    N, n, steps = 1400, 128, 40
+    h = W.grid_spacing(1540.0, 1e6, 12)
+    c_max = 3080.0
+    dt = 0.4 * h / c_max
+    rows = np.asarray([W.TABLE2_ROW, W.tissue_row(8.0, 1.0, 2, 1e6)], np.float64)
+    rng = np.random.default_rng(1400)
+    wc = rng.uniform(1540.0, c_max, (n, n, n)).astype(np.float32)
+    wr = (1040.0 + (wc - 1540.0) * (860.0 / 1540.0)).astype(np.float32)
+    wb = rng.uniform(3.5, 5.5, (n, n, n)).astype(np.float32)
+    wl = (wc > 2300.0).astype(np.uint8)
+    signal = rng.standard_normal((1, steps)).astype(np.float32) * 1e5
+    s0 = n - 52                                       # source, window coordinates
+    r = np.array([s0 - 6, s0, s0 + 6, s0 + 30, s0 + 45])
+    rx, ry, rz = [g.ravel() for g in np.meshgrid(r[:3], r[:3], r[:3], indexing="ij")]
+    rx = np.concatenate([rx[:-2], r[3:]])
+    ry = np.concatenate([ry[:-2], r[3:]])
+    rz = np.concatenate([rz[:-2], r[3:][::-1]])
+
+    def problem(size, off):
+        grid = (size,) * 3
+        prob = W.Problem(shape=grid, h=h, dt=dt, n_relax=2, c=np.full(grid, 1540.0, np.float32),
+                         rho=np.full(grid, 1040.0, np.float32), beta=np.full(grid, 4.0, np.float32),
+                         relax_table=rows, label=np.zeros(grid, np.uint8), bound_cells=(48,) * 3,
+                         trans_cells=(36,) * 3, pml_cp=c_max, fd_r=c_max * dt / h, n_steps=steps)
+        prob.src_idx = prob.flat(np.array([off + s0]), np.array([off + s0]), np.array([off + s0]))
+        prob.src_sig = np.zeros(1, np.int32)
+        prob.src_w = np.ones(1, np.float32)
+        prob.signals = signal
+        prob.rcv_idx = prob.flat(off + rx, off + ry, off + rz)
+        return prob
+
+    small = problem(n, 0)
+    small.c[...], small.rho[...], small.beta[...], small.label[...] = wc, wr, wb, wl
+    big = problem(N, N - n)
+    win = (slice(N - n, N),) * 3
+    big.c[win], big.rho[win], big.beta[win], big.label[win] = wc, wr, wb, wl
+    _say("largest 3D cube %d^3, far-corner %d^3 window, point source and %d receivers, %d steps"
+         % (N, n, len(rx), steps))
+    dom = fw2.from_problem(big, device="cuda:0", cap_steps=steps)
+    del big
+    dom.step(steps)
+    torch.cuda.synchronize()
+    tr = dom.trace[:steps].cpu().numpy()
+    out = dom.read_fields_device(fw2.FIELD_P)
+    pv = dom.field_views(out, fw2.FIELD_P)["p"]
+    f = {"p": pv[win].cpu().numpy()}
+    pv[win] = 0.0
+    outside = float(out.abs().max().item())
+    del out, pv
+    dom.destroy_domain()
+    torch.cuda.empty_cache()
+    ref, rtr = oracle_run(small, steps)
+    _say("largest 3D cube: max |p| outside the window %.2e of the window's peak" % (outside / np.abs(ref.p).max()))
+    assert outside <= 1e-20 * np.abs(ref.p).max()
+    compare(f, tr, ref, rtr, "largest_3d_far_corner", check_all=False, prob=small)
+
+
 # ---------------------------------------------------------- edge cases ---
 
 def test_degenerate_grids():
