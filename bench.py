@@ -527,6 +527,60 @@ def summarize_stats_only(stats_db, name, title, commands):
         fh.write("\n".join(lines) + "\n")
 
 
+CALIBRATION_BYTES = {"copy16": 512 << 20, "mix": 21 * (64 << 20)}   # buffer of each calibration probe
+
+
+def calibration_probe(reps=5):
+    """The library's streaming probes on fixed buffers (random data), reps
+    dispatches each, for the HBM counter passes that check the counters'
+    scale on known-size kernels; prints the bytes each dispatch must move."""
+    import torch
+    from paper_2106_11476_amd import fw2
+    dev = torch.device("cuda:0")
+    out = {}
+    for name, kind in (("copy16", fw2.PROBE_COPY), ("mix", fw2.PROBE_VELOCITY_MIX)):
+        nbytes = CALIBRATION_BYTES[name]
+        buf = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        buf.view(torch.float32).normal_()
+        n = fw2.stream_probe_elements(kind, nbytes)
+        for _ in range(reps):
+            fw2.stream_probe(kind, buf)
+        torch.cuda.synchronize(dev)
+        del buf
+        rd, wr = (16 * n, 16 * n) if kind == fw2.PROBE_COPY else (48 * n, 36 * n)
+        out[name] = {"read_bytes": rd, "write_bytes": wr, "dispatches": reps}
+    print(json.dumps({"calibration_probe": out}))
+    return out
+
+
+def summarize_calibration(fetch_db, write_db, commands):
+    """Write profiles/traffic_calibration_stream_probes.txt: FETCH_SIZE and
+    WRITE_SIZE (KiB per dispatch) of the library's probes against the bytes
+    they must read and write, i.e. the scale factors of the counters measured
+    on two known-size kernels other than the copy the traffic summaries use."""
+    from paper_2106_11476_amd import fw2
+    fetch = {r[0]: r for r in _db_rows(fetch_db, "select name, avg(counter_value), count(*) from pmc_events group by name")}
+    write = {r[0]: r for r in _db_rows(write_db, "select name, avg(counter_value), count(*) from pmc_events group by name")}
+    lines = ["HBM counter scale on known-size kernels: the library's streaming probes (fw2_stream_probe)", "commands:"]
+    lines += ["  " + c for c in commands]
+    for name, kind in (("copy16", fw2.PROBE_COPY), ("mix", fw2.PROBE_VELOCITY_MIX)):
+        n = fw2.stream_probe_elements(kind, CALIBRATION_BYTES[name])
+        rd, wr = (16 * n, 16 * n) if kind == fw2.PROBE_COPY else (48 * n, 36 * n)
+        fk = [k for k in fetch if ("probe_copy16" if name == "copy16" else "probe_mix") in k][0]
+        wk = [k for k in write if ("probe_copy16" if name == "copy16" else "probe_mix") in k][0]
+        f_raw, w_raw = fetch[fk][1], write[wk][1]
+        lines += ["%s_kernel: %s" % (name, fk),
+                  "%s_read_kib_per_dispatch: %.1f" % (name, rd / 1024.0),
+                  "%s_fetch_kib_per_dispatch_raw: %.1f" % (name, f_raw),
+                  "%s_fetch_scale: %.4f" % (name, rd / 1024.0 / f_raw),
+                  "%s_write_kib_per_dispatch: %.1f" % (name, wr / 1024.0),
+                  "%s_write_kib_per_dispatch_raw: %.1f" % (name, w_raw),
+                  "%s_write_scale: %.4f" % (name, wr / 1024.0 / w_raw)]
+    os.makedirs(PROFILES, exist_ok=True)
+    with open(os.path.join(PROFILES, "traffic_calibration_stream_probes.txt"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+
 def summarize_profiles(stats_db, fetch_db, write_db, workload, copy_bytes, commands, n3d=1024, relax=None):
     """Write profiles/*.txt from rocprofv3 results (kernel-trace stats and the
     FETCH_SIZE / WRITE_SIZE passes).  Counter values are KiB per dispatch;
@@ -840,11 +894,21 @@ def main():
     ap.add_argument("--commands", nargs="*", default=[])
     ap.add_argument("--summarize-stats", nargs=3, metavar=("STATS_DB", "NAME", "TITLE"),
                     help="write profiles/kernel_stats_NAME.txt from one kernel-trace database and exit")
+    ap.add_argument("--calibration-probe", action="store_true",
+                    help="only run the library's streaming probes on fixed buffers (for the counter-scale check) and exit")
+    ap.add_argument("--summarize-calibration", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
+                    help="write profiles/traffic_calibration_stream_probes.txt from the two counter passes and exit")
     ap.add_argument("--summarize-adjoint", nargs=3, metavar=("STATS_DB", "FETCH_DB", "WRITE_DB"),
                     help="write the adjoint leg's kernel statistics and traffic summaries and exit")
     ap.add_argument("--profiles-dir", default=PROFILES, help="where the summaries go")
     args = ap.parse_args()
     PROFILES = args.profiles_dir
+    if args.summarize_calibration:
+        summarize_calibration(*args.summarize_calibration, commands=args.commands)
+        return
+    if args.calibration_probe:
+        calibration_probe()
+        return
     if args.summarize_adjoint:
         summarize_adjoint(*args.summarize_adjoint, copy_bytes=args.copy_read_bytes, commands=args.commands)
         return

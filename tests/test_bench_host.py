@@ -92,3 +92,30 @@ def test_stream_reference_relates_the_kernel_to_a_plain_copy(monkeypatch):
     assert r["probe_copy16"]["GBps"] == 6250.0 and r["probe_velocity_mix"]["GBps"] == 5200.0
     r = bench.stream_reference(None, None, {"achieved": 4000.0, "traffic": None, "launch_ms": 2.0})
     assert "kernel_traffic_GBps" not in r
+
+
+def test_calibration_summary_reads_the_counter_scale_of_each_probe(tmp_path, monkeypatch):
+    """summarize_calibration divides the bytes each probe must move by the
+    counters' KiB per dispatch (fake databases with the pmc_events table)."""
+    import sqlite3
+    from paper_2106_11476_amd import fw2
+
+    def db(path, values):
+        con = sqlite3.connect(path)
+        con.execute("create table pmc_events (name text, counter_value real)")
+        for name, v in values:
+            con.executemany("insert into pmc_events values (?, ?)", [(name, v)] * 3)
+        con.commit()
+        con.close()
+        return str(path)
+
+    n_copy = fw2.stream_probe_elements(fw2.PROBE_COPY, bench.CALIBRATION_BYTES["copy16"])
+    n_mix = fw2.stream_probe_elements(fw2.PROBE_VELOCITY_MIX, bench.CALIBRATION_BYTES["mix"])
+    kib = lambda b: b / 1024.0
+    f = db(tmp_path / "f.db", [("ns::probe_copy16(args)", kib(16 * n_copy) / 2), ("ns::probe_mix(args)", kib(48 * n_mix) / 2)])
+    w = db(tmp_path / "w.db", [("ns::probe_copy16(args)", kib(16 * n_copy)), ("ns::probe_mix(args)", kib(36 * n_mix))])
+    monkeypatch.setattr(bench, "PROFILES", str(tmp_path))
+    bench.summarize_calibration(f, w, ["cmd"])
+    vals = bench._profile_values(str(tmp_path / "traffic_calibration_stream_probes.txt"))
+    assert vals["copy16_fetch_scale"] == "2.0000" and vals["mix_fetch_scale"] == "2.0000"
+    assert vals["copy16_write_scale"] == "1.0000" and vals["mix_write_scale"] == "1.0000"
