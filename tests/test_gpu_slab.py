@@ -199,3 +199,39 @@ def test_zero_halos_stay_zero_after_stepping(shape, L):
         sl = [slice(None)] * nd
         sl[nd - 1 - a] = -1
         assert not f["v"][a][tuple(sl)].any(), a
+
+
+def test_benchmark_cube_in_eight_real_slabs_is_bitwise_the_whole_grid_run():
+    """The benchmark's 1024^3 transcranial cube split into eight 1024 x 1024 x
+    128 slabs, one GPU's share each on eight GPUs, stepped with the halo
+    exchange after each phase, gives bit for bit the whole grid's pressure
+    and focal-axis traces after 200 steps, when the pulse is at a third of
+    its peak."""
+    torch = _torch()
+    from paper_2106_11476_amd import fw2, slab
+    steps = 200
+    prob = W.skull_3d(n=1024, L=2)
+    _say("skull_3d 1024^3: whole grid against eight 128-plane slabs, %d steps" % steps)
+    torch.cuda.empty_cache()
+    dom = fw2.from_problem(prob, device="cuda:0", cap_steps=steps)
+    dom.step(steps)
+    torch.cuda.synchronize()
+    p_whole = dom.read_fields_device(fw2.FIELD_P)
+    tr_whole = dom.trace.cpu().numpy()
+    dom.destroy_domain()
+    del dom
+    torch.cuda.empty_cache()
+    ss = slab.SlabSet(prob, list(range(0, 1025, 128)), device="cuda:0", cap_steps=steps)
+    ss.step(steps)
+    torch.cuda.synchronize()
+    whole = p_whole.view(1024, 1024, 1024)
+    for k, d in enumerate(ss.domains):
+        part = d.read_fields_device(fw2.FIELD_P).view(128, 1024, 1024)
+        assert torch.equal(part, whole[128 * k:128 * (k + 1)]), k
+        del part
+    tr_slab = ss.traces()
+    ss.destroy()
+    del p_whole, whole
+    torch.cuda.empty_cache()
+    assert np.array_equal(tr_slab, tr_whole)
+    assert np.abs(tr_whole).max() > 0
